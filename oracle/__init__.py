@@ -1,0 +1,25 @@
+"""FP64 CPU oracle for the log-polar hyperbolic Radon transform.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+link anything in this package: only the test suite, the smoke check and the
+benchmark's CPU-baseline leg use it.  It shares no code with the HIP library.
+
+Two oracles live here, both written from the paper (Nikitin, Andersson,
+Carlsson, Duchkov, "Fast hyperbolic Radon transform represented as
+convolutions in log-polar coordinates"):
+
+* `direct`   - the definition, eq. (1) (label Rhdef): summation over
+               hyperbolas with cubic interpolation in time (Section 5), and
+               its exact transpose.
+* `logpolar` - the discrete log-polar method of Sections 2-4, step by step in
+               the paper's order (resampling with the 1/(2 sqrt y) weight,
+               B-spline smearing, FFT convolution with the kernel spectrum,
+               B-spline interpolation back to (tau, q)), and its transpose.
+
+Supporting modules: `geometry` (rescaling, sector placement, coordinate maps,
+lattice sizing), `bspline` (cubic cardinal B-spline), `kernel` (the spectrum of
+zeta by quadrature), `ista` (soft-thresholding iterations of Section 3).
+All arithmetic is float64.  Readings of points where the paper is silent or
+garbled are stated in each function's docstring.
+"""
+from . import bspline, geometry, kernel, logpolar, direct  # noqa: F401

@@ -1,0 +1,14 @@
+"""Seeded synthetic CMP gathers and grid descriptions.
+
+This package only draws inputs: grid descriptions, Ricker-wavelet hyperbolic
+events, noise and trace masks.  It holds none of the transform's arithmetic, so
+both the FP64 oracle and the GPU library can be fed from it without sharing any
+code of the method.
+"""
+from .gathers import (GridDesc, CONFIGS, config_desc, ricker, ricker_gather,
+                      config_gather, gaussian_sy_gather, trace_mask,
+                      batch_descs, batch_gathers, random_pair)
+
+__all__ = ["GridDesc", "CONFIGS", "config_desc", "ricker", "ricker_gather",
+           "config_gather", "gaussian_sy_gather", "trace_mask", "batch_descs",
+           "batch_gathers", "random_pair"]
