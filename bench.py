@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of the log-polar hyperbolic Radon transform on one MI355X.
+
+A step is one forward plus one adjoint transform of a device-resident CMP
+gather: 2048 time samples (dt = 2 ms) x 1024 offsets (0..4 km) -> Radon panel
+2048 taus x 1024 slownesses (v in [1.5, 4] km/s), 100 Ricker events at 30 Hz,
+log-polar lattice 2160 x 3072 (oversampling 2).  Prints one JSON line.
+
+Beside the throughput it reports: per-kernel HIP-event timings and the HBM
+roofline of the dominant kernel, the float32 GPU direct summation over
+hyperbolas (the paper's reference method) on the same gather, the rel-L2 of
+both directions against the FP64 oracle, and the FP64 oracle itself timed on
+the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("gathers/s fwd+adj at 2048x1024 FP32 vs GPU direct sum; "
+          "rel-L2 vs FP64; HBM GB/s")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_alg_bytes(info, desc):
+    """Algorithmic HBM bytes per launch of each kernel (inputs read once,
+    outputs written once), same order as Plan.STAGES."""
+    U = info["row_hi"] - info["row_lo"]
+    spec = 8.0 * info["k1_kept"] * U
+    kmul = 8.0 * info["k1_kept"] * info["k2_kept"]
+    data_in = 4.0 * info["n_kept"]
+    data_out = 4.0 * desc.nx * desc.nt
+    radon = 4.0 * desc.nq * desc.ntau
+    return [data_in + spec, 2 * spec + kmul, spec + radon,
+            radon + spec, 2 * spec + kmul, spec + data_out]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--direct-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the transform of a gather runs on "
+              "a single device (independent gathers would shard across GPUs with "
+              "no communication); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1604_07651_amd.hrt import Plan
+
+    torch.cuda.set_device(0)
+    desc = synth.config_desc("c3")
+    log("generating the gather")
+    f64 = synth.config_gather("c3")
+    f = torch.from_numpy(f64.astype(np.float32)).cuda()
+    log("plan")
+    plan = Plan(desc)
+    info = plan.info
+    g = torch.empty(plan.radon_shape, device="cuda")
+    fa = torch.empty(plan.data_shape, device="cuda")
+
+    def step():
+        plan.forward(f, out=g)
+        plan.adjoint(g, out=fa)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"timed {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec_per_step = (t1 - t0) / args.steps
+    value = 1.0 / sec_per_step
+
+    # per-kernel HIP events on the launch stream, over the same number of steps
+    log("per-kernel event timing")
+    plan.profile_begin(6 * args.steps)
+    for _ in range(args.steps):
+        step()
+    prof = plan.profile_end()
+    alg = kernel_alg_bytes(info, desc)
+    kernels = {}
+    for i, (name, (ms, n)) in enumerate(prof.items()):
+        avg_us = 1e3 * ms / max(n, 1)
+        kernels[name] = {"avg_us": round(avg_us, 3), "launches": n,
+                         "alg_bytes": alg[i],
+                         "gbs": round(alg[i] / (avg_us * 1e-6) / 1e9, 1) if avg_us > 0 else None}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
+    achieved = kernels[dom]["gbs"]
+
+    # reference method on the GPU: direct summation over hyperbolas
+    log("GPU direct summation")
+    gd = torch.empty_like(g)
+    fd = torch.empty_like(fa)
+    plan.direct_forward(f, out=gd)
+    plan.direct_adjoint(g, out=fd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.direct_steps):
+        plan.direct_forward(f, out=gd)
+        plan.direct_adjoint(g, out=fd)
+    torch.cuda.synchronize()
+    direct_sec = (time.perf_counter() - t0) / args.direct_steps
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "gathers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec_per_step * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "single CMP gather 2048x1024 (dt 2 ms, offsets 0-4 km) "
+                               "-> Radon 2048x1024 (v 1.5-4 km/s), 100 Ricker events "
+                               "30 Hz, forward+adjoint, log-polar lattice "
+                               f"{info['m_theta']}x{info['m_rho']}, oversampling 2",
+                   "nt": desc.nt, "nx": desc.nx, "ntau": desc.ntau, "nq": desc.nq},
+        "hbm_gbs_step": round((info["alg_bytes_fwd"] + info["alg_bytes_adj"])
+                              / sec_per_step / 1e9, 1),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "kernels": kernels,
+        "direct_sum": {"gathers_per_s": round(1.0 / direct_sec, 3),
+                       "ms_fwd_adj": round(direct_sec * 1e3, 3),
+                       "speedup_log_polar": round(direct_sec / sec_per_step, 1)},
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle.logpolar import LogPolarOracle
+        log("FP64 oracle plan (not timed)")
+        ora = LogPolarOracle(desc)
+        log("FP64 oracle forward + adjoint (timed)")
+        g64 = g.double().cpu().numpy()
+        t0 = time.perf_counter()
+        gref = ora.forward(f64)
+        faref = ora.adjoint(g64)
+        cpu_sec = time.perf_counter() - t0
+        gg = g.double().cpu().numpy()
+        ff = fa.double().cpu().numpy()
+        out["rel_l2_vs_fp64"] = {
+            "forward": float(np.linalg.norm(gg - gref) / np.linalg.norm(gref)),
+            "adjoint": float(np.linalg.norm(ff - faref) / np.linalg.norm(faref))}
+        out["cpu_baseline"] = {"value": round(1.0 / cpu_sec, 4), "unit": "gathers/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "one full 2048x1024 gather, FP64 log-polar "
+                                         "oracle forward+adjoint (numpy, one thread), "
+                                         "plan excluded",
+                               "seconds": round(cpu_sec, 2),
+                               "host_cores_available": len(os.sched_getaffinity(0))}
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,154 @@
+/*
+ * hrt.h - C ABI of the MI355X (gfx950) hyperbolic Radon transform library.
+ *
+ * The library evaluates the forward hyperbolic Radon transform of a CMP
+ * gather and its exact transpose with the log-polar method of Nikitin,
+ * Andersson, Carlsson and Duchkov, "Fast hyperbolic Radon transform
+ * represented as convolutions in log-polar coordinates":
+ *
+ *   forward  R_h f(tau, q) = integral over 0 <= x <= X of
+ *                            f(sqrt(tau^2 + q^2 x^2), x) dx     (eq. Rhdef,
+ *            one-sided since data exist only for x >= 0), computed as
+ *            (t, x) -> (t^2, x^2) resampling with the 1/(2 sqrt y) weight
+ *            (eq. f), cubic B-spline smearing onto an equally spaced
+ *            log-polar lattice (eq. B3tx2), FFT convolution with the
+ *            precomputed kernel spectrum (eqs. finiteconv, lok), and B-spline
+ *            interpolation back to (tau, q) (eq. B3tauq);
+ *   adjoint  the transpose of that discrete operator, <R f, g> = <f, R* g>
+ *            (Section 3, eq. inner), by running the chain in reverse.
+ *
+ * Grids follow the paper's statement of the problem (Section 2.2, eqs.
+ * Rgrid, Qgrid): the gather is sampled regularly on 0 <= t <= T,
+ * x0 <= x <= X and is zero outside; the Radon panel is regular in tau and q.
+ *
+ * Conventions shared by every entry point
+ *  - All functions return hrt_status; HRT_OK is 0.  No C++ exception crosses
+ *    the ABI.  On failure hrt_last_error() returns a thread-local message.
+ *  - Array arguments of the transforms are DEVICE pointers to contiguous
+ *    float32 arrays on the device the plan was created on:
+ *      data   f[k][j] = f(t_j, x_k),    t_j = j*dt,            x_k = x0 + k*dx
+ *      Radon  g[l][i] = g(tau_i, q_l),  tau_i = tau0 + i*dtau, q_l = q0 + l*dq
+ *    The caller owns them.  Inputs and outputs must not overlap.
+ *  - Units: t, tau, dt, dtau in s; x in km; q in s/km (any consistent units
+ *    work: the transform scales with the offset unit).
+ *  - hrt_forward / hrt_adjoint / hrt_direct_* only enqueue kernels on the
+ *    given HIP stream (NULL = the default stream); they never allocate,
+ *    never synchronize the host, and overwrite their output completely.
+ *  - A plan may be used by one stream at a time; distinct plans are
+ *    independent.  Device faults surface as HRT_ERR_HIP on a later call.
+ */
+#ifndef HRT_H_
+#define HRT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hrt_plan_s* hrt_plan_t;
+
+typedef enum {
+  HRT_OK = 0,
+  HRT_ERR_INVALID_ARG = 1, /* null pointer, bad size, bad handle contents   */
+  HRT_ERR_GEOMETRY = 2,    /* grids that the method cannot represent        */
+  HRT_ERR_OOM = 3,         /* device allocation failed                      */
+  HRT_ERR_HIP = 4,         /* a HIP call or kernel launch failed            */
+  HRT_ERR_BAD_HANDLE = 5,  /* destroyed or foreign plan handle              */
+  HRT_ERR_UNSUPPORTED = 6  /* sizes beyond what the kernels were built for  */
+} hrt_status;
+
+/* Grid description (Section 2.2, eqs. Rgrid and Qgrid).
+ * Requirements (checked, HRT_ERR_INVALID_ARG otherwise):
+ *   nt, nx, ntau, nq >= 4;  dt, dx, dtau, dq > 0;  q0 >= 0;  x0 >= 0;
+ *   tau0 >= 0 and tau0 + (ntau-1)*dtau <= (nt-1)*dt;  oversample >= 1.5. */
+typedef struct {
+  int32_t nt, nx;      /* time samples per trace, number of traces          */
+  double dt, x0, dx;   /* t_j = j*dt, x_k = x0 + k*dx                       */
+  int32_t ntau, nq;    /* Radon samples: tau_i = tau0 + i*dtau, q_l = q0+l*dq */
+  double tau0, dtau, q0, dq;
+  double oversample;   /* log-polar oversampling sigma (2.0 is the default) */
+  int32_t flags;       /* reserved, must be 0                               */
+} hrt_desc;
+
+/* What a plan computed (all host values). */
+typedef struct {
+  double T, X;                    /* rescaling lengths, eq. hypnorm         */
+  double alpha, beta, a, O1, O2;  /* sector and square, Section 2.1         */
+  double a_r;                     /* first non-zero log-polar radius        */
+  double dtheta0, drho0;          /* eq. lpsamples maxima                   */
+  double dtheta, drho, beta_k;    /* lattice spacing, kernel half-width     */
+  int32_t m_theta, m_rho;         /* lattice size (angle, log radius)       */
+  int32_t k1_kept, k2_kept;       /* non-negative kept frequencies per axis */
+  int32_t row_lo, row_hi;         /* lattice rows the data and outputs use  */
+  int32_t band_rows, n_bands;     /* row bands of the spread/gather kernels */
+  int64_t n_kept;                 /* data samples inside the trapezoid      */
+  int64_t workspace_bytes;        /* device memory owned by the plan        */
+  double alg_bytes_fwd;           /* algorithmic HBM bytes of one forward   */
+  double alg_bytes_adj;           /* ... and of one adjoint                 */
+} hrt_info;
+
+/* Geometry and sizes only: the plan's host computation (rescaling, sector
+ * placement, lattice spacing, row bands) with no GPU call.  Usable on a
+ * machine without a GPU.  Returns HRT_ERR_INVALID_ARG for bad grids. */
+hrt_status hrt_plan_describe(const hrt_desc* desc, hrt_info* out);
+
+/* Build a plan on the current HIP device: the host geometry, the kernel
+ * spectrum of eq. finiteconv evaluated by Gauss-Legendre quadrature in
+ * float64 on the device, the per-trace and per-slowness tables, and all
+ * device workspace.  Synchronizes the device once.  *out receives the
+ * handle, to be released with hrt_plan_destroy. */
+hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out);
+
+/* Forward transform g = R_h f: f is float32[nx][nt], g is float32[nq][ntau],
+ * both device pointers.  `stream` is a hipStream_t (NULL = default). */
+hrt_status hrt_forward(hrt_plan_t plan, const float* f, float* g,
+                       void* stream);
+
+/* Adjoint transform f = R_h^T g (exact transpose of hrt_forward up to
+ * float32 rounding): g is float32[nq][ntau], f is float32[nx][nt]; samples
+ * outside the trapezoid t >= q0*x are set to zero. */
+hrt_status hrt_adjoint(hrt_plan_t plan, const float* g, float* f,
+                       void* stream);
+
+/* Reference method of Section 5: direct summation over hyperbolas with
+ * Keys cubic interpolation in time and the trapezoid rule in offset, in
+ * float32 on the GPU (forward), and its exact transpose (adjoint).  Same
+ * arrays and stream rules as hrt_forward / hrt_adjoint. */
+hrt_status hrt_direct_forward(hrt_plan_t plan, const float* f, float* g,
+                              void* stream);
+hrt_status hrt_direct_adjoint(hrt_plan_t plan, const float* g, float* f,
+                              void* stream);
+
+/* Copy of the plan's summary. */
+hrt_status hrt_query(hrt_plan_t plan, hrt_info* out);
+
+/* Copy the kernel multiplier K[k1][k2] (k1 < k1_kept, 0 <= k2 < k2_kept,
+ * complex as two floats, unnormalised: zeta^/(dtheta drho b^2 b^2) of
+ * eq. B3tauq) to host memory `host_out` of 2*k1_kept*k2_kept floats.
+ * Synchronizes the device. */
+hrt_status hrt_plan_kernel(hrt_plan_t plan, float* host_out);
+
+/* Per-kernel timing for measurement tools.  hrt_profile_begin creates
+ * 2*max_records HIP events (the only allocation; none happens later) and
+ * from then on hrt_forward / hrt_adjoint record an event on the launch
+ * stream before and after each of their kernels, until max_records kernels
+ * have been recorded.  hrt_profile_end synchronizes on the recorded events,
+ * writes the summed milliseconds and the launch count per kernel into
+ * ms_sum[6] and count[6] (order: forward spread+row FFT, forward column
+ * pass, forward row inverse FFT+gather, then the same three of the
+ * adjoint) and releases the events.  Either output may be NULL. */
+hrt_status hrt_profile_begin(hrt_plan_t plan, int32_t max_records);
+hrt_status hrt_profile_end(hrt_plan_t plan, double* ms_sum, int64_t* count);
+
+/* Release a plan and its device memory.  NULL is ignored. */
+void hrt_plan_destroy(hrt_plan_t plan);
+
+const char* hrt_status_string(hrt_status s);
+const char* hrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HRT_H_ */

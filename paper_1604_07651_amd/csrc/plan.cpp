@@ -1,0 +1,388 @@
+// Host float64 plan: rescaling (eq. hypnorm), sector and square placement
+// (Section 2.1), the coordinate maps T and P1 (eqs. transformT, transformP),
+// lattice spacing (eq. lpsamples) and extent, row bands and per-slowness
+// tables.  Compiled with -ffp-contract=off: the trapezoid cut is an integer
+// decision that must come out exactly as the definition j*dt >= q0*x_k
+// evaluated in float64.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <thread>
+
+namespace hrt {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool is_even_5smooth(int64_t m) {
+  if (m < 2 || (m & 1)) return false;
+  for (int p : {2, 3, 5})
+    while (m % p == 0) m /= p;
+  return m == 1;
+}
+
+int64_t next_even_5smooth(int64_t n) {
+  int64_t m = std::max<int64_t>(n, 2);
+  while (!is_even_5smooth(m)) ++m;
+  return m;
+}
+
+// Number of integers k >= 0 with 2 sigma k < M: the non-negative half of the
+// band-limit rectangle L along one axis.
+int kept_nonneg(int M, double sigma) {
+  int k = 0;
+  while (2.0 * sigma * static_cast<double>(k) < static_cast<double>(M)) ++k;
+  return k;
+}
+
+struct TraceScan {
+  double dphi = 0, deta = 0, eta_min = 1e300, eta_max = -1e300;
+  int64_t kept = 0;
+};
+
+}  // namespace
+
+FftFactors factor_fft(int n) {
+  FftFactors f;
+  f.n = n;
+  int m = n, p2 = 0;
+  while (m % 2 == 0) { m /= 2; ++p2; }
+  int p3 = 0;
+  while (m % 3 == 0) { m /= 3; ++p3; }
+  int p5 = 0;
+  while (m % 5 == 0) { m /= 5; ++p5; }
+  if (m != 1) { f.npass = -1; return f; }
+  auto push = [&](int r) {
+    if (f.npass < kMaxPasses) f.radix[f.npass] = r;
+    ++f.npass;
+  };
+  // powers of two: radix 8 where possible, fours for the remainder, a
+  // single radix 2 only when p2 == 1
+  if (p2 == 1) {
+    push(2);
+  } else {
+    int r = p2 % 3;
+    int eights = (r == 1) ? (p2 - 4) / 3 : p2 / 3;
+    for (int i = 0; i < eights; ++i) push(8);
+    if (r == 1) { push(4); push(4); }
+    if (r == 2) push(4);
+  }
+  for (int i = 0; i < p3; ++i) push(3);
+  for (int i = 0; i < p5; ++i) push(5);
+  if (f.npass > kMaxPasses) f.npass = -1;
+  return f;
+}
+
+void bspline_weights(double f, double w[4]) {
+  const double g = 1.0 - f;
+  w[0] = g * g * g / 6.0;
+  w[1] = 2.0 / 3.0 - f * f + 0.5 * f * f * f;
+  w[2] = 2.0 / 3.0 - g * g + 0.5 * g * g * g;
+  w[3] = f * f * f / 6.0;
+}
+
+void gauss_legendre(int order, int panels, double lo, double hi,
+                    std::vector<double>& nodes, std::vector<double>& weights) {
+  std::vector<double> x(order), w(order);
+  for (int i = 0; i < (order + 1) / 2; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (order + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= order; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = order * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    // recompute the derivative at the converged node
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= order; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = order * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = -z;
+    x[order - 1 - i] = z;
+    w[i] = w[order - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  nodes.resize(static_cast<size_t>(order) * panels);
+  weights.resize(nodes.size());
+  const double h = (hi - lo) / panels;
+  for (int p = 0; p < panels; ++p) {
+    const double mid = lo + (p + 0.5) * h;
+    for (int i = 0; i < order; ++i) {
+      nodes[static_cast<size_t>(p) * order + i] = mid + 0.5 * h * x[i];
+      weights[static_cast<size_t>(p) * order + i] = 0.5 * h * w[i];
+    }
+  }
+}
+
+static hrt_status fail(std::string& err, hrt_status s, const char* msg) {
+  err = msg;
+  return s;
+}
+
+hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
+                          std::string& err) {
+  if (d.nt < 4 || d.nx < 4 || d.ntau < 4 || d.nq < 4)
+    return fail(err, HRT_ERR_INVALID_ARG, "every grid needs at least 4 samples");
+  if (!(d.dt > 0) || !(d.dx > 0) || !(d.dtau > 0) || !(d.dq > 0))
+    return fail(err, HRT_ERR_INVALID_ARG, "sampling intervals must be positive");
+  if (!(d.q0 >= 0) || !(d.x0 >= 0) || !(d.tau0 >= 0))
+    return fail(err, HRT_ERR_INVALID_ARG, "need q0 >= 0, x0 >= 0, tau0 >= 0");
+  if (d.tau0 + (d.ntau - 1) * d.dtau > (d.nt - 1) * d.dt)
+    return fail(err, HRT_ERR_INVALID_ARG, "tau range exceeds the time range");
+  if (!(d.oversample >= 1.5))
+    return fail(err, HRT_ERR_INVALID_ARG, "oversampling must be >= 1.5");
+  if (d.flags != 0)
+    return fail(err, HRT_ERR_INVALID_ARG, "flags must be 0");
+  if (static_cast<int64_t>(d.nt) * d.nx > (int64_t(1) << 31) ||
+      static_cast<int64_t>(d.ntau) * d.nq > (int64_t(1) << 31))
+    return fail(err, HRT_ERR_UNSUPPORTED, "panels above 2^31 samples");
+
+  g = Geometry{};
+  g.d = d;
+  // eq. hypnorm: rescale to the unit square
+  g.T = (d.nt - 1) * d.dt;
+  g.X = d.x0 + (d.nx - 1) * d.dx;
+  const double qh_min = d.q0 * g.X / g.T;
+  const double qh_max = (d.q0 + (d.nq - 1) * d.dq) * g.X / g.T;
+
+  // Section 2.1: sector opening and mid angle, inscribed square
+  const double psi_min = std::atan(qh_min * qh_min);
+  const double psi_max = std::atan(qh_max * qh_max);
+  g.beta = psi_max - psi_min;
+  g.alpha = 0.5 * (psi_max + psi_min);
+  if (!(g.beta > 1e-9))
+    return fail(err, HRT_ERR_GEOMETRY, "slowness range too narrow for a sector");
+  const double s2a = std::sin(2.0 * g.alpha);
+  const double sb = std::sin(g.beta), cb = std::cos(g.beta);
+  g.a = sb / std::sqrt(s2a * sb + cb * (s2a + sb) + 1.0);
+  // corners (s,y) = (0,0) and (1,1) on the -beta/2 and +beta/2 rays
+  g.O1 = g.a * std::sin(g.alpha + kPi / 4) / (std::sqrt(2.0) * std::tan(g.beta / 2));
+  g.O2 = g.a * std::cos(g.alpha + kPi / 4) * std::tan(g.beta / 2) / std::sqrt(2.0);
+  g.ca = std::cos(g.alpha);
+  g.sa = std::sin(g.alpha);
+  const double Au = g.a * (g.ca * -0.5 - g.sa * -0.5) + g.O1;
+  const double Av = g.a * (g.sa * -0.5 + g.ca * -0.5) + g.O2;
+  g.a_r = std::hypot(Au, Av) * cb;
+  g.AeA = Au * g.ca + Av * g.sa;
+  if (!(g.a_r > 0) || !(g.AeA > 0))
+    return fail(err, HRT_ERR_GEOMETRY, "degenerate log-polar placement");
+
+  // trapezoid: keep (j, k) iff j*dt >= q0*(x0 + k*dx)
+  g.jmin.assign(d.nx, d.nt);
+  for (int k = 0; k < d.nx; ++k) {
+    const double xk = d.x0 + static_cast<double>(k) * d.dx;
+    const double thr = d.q0 * xk;
+    int j = static_cast<int>(std::max(0.0, std::floor(thr / d.dt) - 2.0));
+    while (j < d.nt && !(static_cast<double>(j) * d.dt >= thr)) ++j;
+    while (j > 0 && static_cast<double>(j - 1) * d.dt >= thr) --j;
+    g.jmin[k] = j;
+  }
+
+  // data samples mapped by (t^2, x^2) -> T -> P1; eq. lpsamples maxima over
+  // neighbour pairs with both samples kept
+  auto map = [&](int j, int k, double& phi, double& eta) {
+    const double th = (static_cast<double>(j) * d.dt) / g.T;
+    const double xh = (d.x0 + static_cast<double>(k) * d.dx) / g.X;
+    const double ds = th * th - 0.5, dy = xh * xh - 0.5;
+    const double u = g.a * (g.ca * ds - g.sa * dy) + g.O1;
+    const double v = g.a * (g.sa * ds + g.ca * dy) + g.O2;
+    phi = std::atan2(v, u);
+    eta = 0.5 * std::log(u * u + v * v);
+  };
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  nth = std::min<unsigned>(nth, static_cast<unsigned>(d.nx));
+  std::vector<TraceScan> part(nth);
+  auto scan = [&](unsigned w) {
+    TraceScan& s = part[w];
+    const int k0 = static_cast<int>(static_cast<int64_t>(d.nx) * w / nth);
+    const int k1 = static_cast<int>(static_cast<int64_t>(d.nx) * (w + 1) / nth);
+    std::vector<double> pp(d.nt), pe(d.nt), cp(d.nt), ce(d.nt);
+    // previous trace (k0 - 1) for the offset-neighbour differences
+    if (k0 > 0)
+      for (int j = g.jmin[k0 - 1]; j < d.nt; ++j) map(j, k0 - 1, pp[j], pe[j]);
+    for (int k = k0; k < k1; ++k) {
+      const int jm = g.jmin[k];
+      for (int j = jm; j < d.nt; ++j) {
+        map(j, k, cp[j], ce[j]);
+        s.eta_min = std::min(s.eta_min, ce[j]);
+        s.eta_max = std::max(s.eta_max, ce[j]);
+        if (j > jm) {
+          s.dphi = std::max(s.dphi, std::fabs(cp[j] - cp[j - 1]));
+          s.deta = std::max(s.deta, std::fabs(ce[j] - ce[j - 1]));
+        }
+        if (k > 0 && j >= g.jmin[k - 1]) {
+          s.dphi = std::max(s.dphi, std::fabs(cp[j] - pp[j]));
+          s.deta = std::max(s.deta, std::fabs(ce[j] - pe[j]));
+        }
+      }
+      s.kept += d.nt - jm;
+      std::swap(pp, cp);
+      std::swap(pe, ce);
+    }
+  };
+  {
+    std::vector<std::thread> ts;
+    for (unsigned w = 1; w < nth; ++w) ts.emplace_back(scan, w);
+    scan(0);
+    for (auto& t : ts) t.join();
+  }
+  double eta_min = 1e300, eta_max = -1e300;
+  for (const auto& s : part) {
+    g.dtheta0 = std::max(g.dtheta0, s.dphi);
+    g.drho0 = std::max(g.drho0, s.deta);
+    eta_min = std::min(eta_min, s.eta_min);
+    eta_max = std::max(eta_max, s.eta_max);
+    g.n_kept += s.kept;
+  }
+  if (!(g.dtheta0 > 0) || !(g.drho0 > 0))
+    return fail(err, HRT_ERR_GEOMETRY, "kept samples do not span the lattice");
+
+  // lattice: spacing, kernel half-width, extent (even 5-smooth sizes)
+  g.sigma = d.oversample;
+  g.dtheta = g.dtheta0 / g.sigma;
+  g.drho = g.drho0 / g.sigma;
+  g.beta_k = g.beta + 4.0 * g.dtheta;
+  if (!(g.beta_k < 1.5))
+    return fail(err, HRT_ERR_GEOMETRY, "sector too wide (beta_k >= 1.5 rad)");
+  const double ln_ar = std::fabs(std::log(g.a_r));
+  const double ln_cb = std::fabs(std::log(std::cos(g.beta_k)));
+  const double mt_min = std::ceil(2.0 * g.beta_k / g.dtheta) + 1.0;
+  const double mr_min = std::ceil((ln_ar + ln_cb) / g.drho) + 9.0;
+  if (mt_min > 1e6 || mr_min > 1e6)
+    return fail(err, HRT_ERR_UNSUPPORTED, "log-polar lattice above 10^6 per axis");
+  g.Mt = static_cast<int>(next_even_5smooth(static_cast<int64_t>(mt_min)));
+  g.Mr = static_cast<int>(next_even_5smooth(static_cast<int64_t>(mr_min)));
+  g.K1 = kept_nonneg(g.Mt, g.sigma);
+  g.K2 = kept_nonneg(g.Mr, g.sigma);
+
+  // placement on the lattice (integer shifts leave the circular
+  // convolution unchanged)
+  g.ctheta = g.Mt / 2;
+  g.crho = static_cast<int>(std::ceil(ln_ar / g.drho)) + 3;
+  // Radon-side radii: e^rho = A + B tau^2, monotone in tau
+  const int nq = d.nq;
+  g.qA.resize(nq);
+  g.qB.resize(nq);
+  g.q_i0.resize(nq);
+  g.q_w.resize(4 * static_cast<size_t>(nq));
+  g.q_scale.resize(nq);
+  double rho_min = 1e300, rho_max = -1e300;
+  const double th_lo = d.tau0 / g.T;
+  const double th_hi = (d.tau0 + (d.ntau - 1) * d.dtau) / g.T;
+  for (int l = 0; l < nq; ++l) {
+    const double qh = (d.q0 + l * d.dq) * g.X / g.T;
+    const double psi = std::atan(qh * qh);
+    const double theta = g.alpha - psi;
+    g.qA[l] = g.O1 * std::cos(theta) + g.O2 * std::sin(theta) +
+              0.5 * g.a * (std::sin(psi) - std::cos(psi));
+    g.qB[l] = g.a * std::cos(psi);
+    g.q_scale[l] = static_cast<float>(g.X * std::cos(psi) / g.a);
+    const double xg = theta / g.dtheta + g.ctheta;
+    const double i0 = std::floor(xg);
+    double w[4];
+    bspline_weights(xg - i0, w);
+    g.q_i0[l] = static_cast<int32_t>(i0) - 1;
+    for (int t = 0; t < 4; ++t) g.q_w[4 * l + t] = static_cast<float>(w[t]);
+    const double e_lo = g.qA[l] + g.qB[l] * th_lo * th_lo;
+    const double e_hi = g.qA[l] + g.qB[l] * th_hi * th_hi;
+    if (!(e_lo > 0))
+      return fail(err, HRT_ERR_GEOMETRY, "Radon sample maps to a non-positive radius");
+    rho_min = std::min(rho_min, std::log(e_lo));
+    rho_max = std::max(rho_max, std::log(e_hi));
+  }
+  const double yg_min = std::min(eta_min, rho_min) / g.drho + g.crho;
+  const double yg_max = std::max(eta_max, rho_max) / g.drho + g.crho;
+  g.u0 = static_cast<int>(std::floor(yg_min)) - 2;
+  g.u0 -= (g.u0 & 1);
+  g.u1 = static_cast<int>(std::floor(yg_max)) + 4;
+  if ((g.u1 - g.u0) & 1) ++g.u1;
+  if (g.u0 < 0 || g.u1 > g.Mr)
+    return fail(err, HRT_ERR_GEOMETRY, "points fall outside the log-polar lattice");
+  const int xq_min = *std::min_element(g.q_i0.begin(), g.q_i0.end());
+  const int xq_max = *std::max_element(g.q_i0.begin(), g.q_i0.end()) + 3;
+  if (xq_min < 0 || xq_max >= g.Mt)
+    return fail(err, HRT_ERR_GEOMETRY, "angles fall outside the log-polar lattice");
+
+  // row bands: the gather kernel holds band + 3 halo rows as complex pairs
+  auto band_fits = [&](int R) {
+    const int64_t pairs = (R + 4) / 2;
+    return pairs * g.Mt * 8 <= lds_bytes && pairs * g.Mt <= kCapRow;
+  };
+  g.R = 8;
+  while (g.R > 2 && !band_fits(g.R)) g.R -= 2;
+  if (!band_fits(g.R))
+    return fail(err, HRT_ERR_UNSUPPORTED, "angle axis too long for the LDS row bands");
+  if (static_cast<int64_t>(g.Mr) * 8 > lds_bytes || g.Mr > kCapCol)
+    return fail(err, HRT_ERR_UNSUPPORTED, "log-radius axis too long for an LDS column");
+  g.nbands = (g.u1 - g.u0 + g.R - 1) / g.R;
+
+  g.fft_t = factor_fft(g.Mt);
+  g.fft_r = factor_fft(g.Mr);
+  if (g.fft_t.npass < 0 || g.fft_r.npass < 0)
+    return fail(err, HRT_ERR_GEOMETRY, "lattice size is not 5-smooth");
+  return HRT_OK;
+}
+
+void alg_bytes_kernels(const Geometry& g, bool adjoint, double out[3]) {
+  const double U = g.u1 - g.u0;
+  const double spec = 8.0 * g.K1 * U;  // complex64 half spectrum, used rows
+  const double n_data_in = 4.0 * static_cast<double>(g.n_kept);
+  const double n_data_out = 4.0 * static_cast<double>(g.d.nx) * g.d.nt;
+  const double n_radon = 4.0 * static_cast<double>(g.d.nq) * g.d.ntau;
+  out[0] = (adjoint ? n_radon : n_data_in) + spec;
+  out[1] = 2.0 * spec + 8.0 * g.K1 * static_cast<double>(g.K2);
+  out[2] = spec + (adjoint ? n_data_out : n_radon);
+}
+
+double alg_bytes_forward(const Geometry& g) {
+  double b[3];
+  alg_bytes_kernels(g, false, b);
+  return b[0] + b[1] + b[2];
+}
+
+double alg_bytes_adjoint(const Geometry& g) {
+  double b[3];
+  alg_bytes_kernels(g, true, b);
+  return b[0] + b[1] + b[2];
+}
+
+void fill_info(const Geometry& g, hrt_info* o) {
+  o->T = g.T;
+  o->X = g.X;
+  o->alpha = g.alpha;
+  o->beta = g.beta;
+  o->a = g.a;
+  o->O1 = g.O1;
+  o->O2 = g.O2;
+  o->a_r = g.a_r;
+  o->dtheta0 = g.dtheta0;
+  o->drho0 = g.drho0;
+  o->dtheta = g.dtheta;
+  o->drho = g.drho;
+  o->beta_k = g.beta_k;
+  o->m_theta = g.Mt;
+  o->m_rho = g.Mr;
+  o->k1_kept = g.K1;
+  o->k2_kept = g.K2;
+  o->row_lo = g.u0;
+  o->row_hi = g.u1;
+  o->band_rows = g.R;
+  o->n_bands = g.nbands;
+  o->n_kept = g.n_kept;
+  o->workspace_bytes = 0;
+  o->alg_bytes_fwd = alg_bytes_forward(g);
+  o->alg_bytes_adj = alg_bytes_adjoint(g);
+}
+
+}  // namespace hrt

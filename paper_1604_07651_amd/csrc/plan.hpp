@@ -1,0 +1,82 @@
+// Host-side plan of the log-polar hyperbolic Radon transform: float64
+// geometry, lattice sizing, row bands and the small per-trace / per-slowness
+// tables the kernels read.  Pure C++ (no HIP), so hrt_plan_describe works on
+// a machine without a GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hrt.h"
+
+namespace hrt {
+
+constexpr int kMaxPasses = 24;
+// Complex values a band kernel's batched row FFT may hold (bounds register
+// staging per thread) and the longest column FFT.
+constexpr int kCapRow = 12288;
+constexpr int kCapCol = 8192;
+
+// Mixed-radix factorisation of an FFT length (radices 2, 3, 4, 5, 8).
+struct FftFactors {
+  int n = 0;
+  int npass = 0;
+  int radix[kMaxPasses] = {};
+};
+
+FftFactors factor_fft(int n);
+
+// Everything the plan derives from the grids (Sections 2.1, 2.2, 4).
+struct Geometry {
+  hrt_desc d{};
+  // eq. hypnorm
+  double T = 0, X = 0;
+  // Section 2.1: sector, square, first contribution
+  double alpha = 0, beta = 0, a = 0, O1 = 0, O2 = 0, a_r = 0;
+  double ca = 0, sa = 0;      // cos(alpha), sin(alpha)
+  double AeA = 0;             // (corner A) . (cos alpha, sin alpha) > 0
+  // eq. lpsamples and lattice extent
+  double dtheta0 = 0, drho0 = 0, dtheta = 0, drho = 0, beta_k = 0, sigma = 0;
+  int Mt = 0, Mr = 0;         // lattice size (angle, log radius)
+  int K1 = 0, K2 = 0;         // non-negative frequencies inside L per axis
+  // lattice placement: node m sits at theta = (m - ctheta) dtheta, node n at
+  // rho = (n - crho) drho; all used nodes fall inside the array.
+  int ctheta = 0, crho = 0;
+  int u0 = 0, u1 = 0;         // lattice rows touched by any point [u0, u1)
+  int R = 0, nbands = 0;      // row band height (even) and band count
+  int64_t n_kept = 0;
+  std::vector<int32_t> jmin;  // [nx] first kept time sample of each trace
+  // Radon side, per slowness l
+  std::vector<double> qA, qB;     // e^rho = qA + qB tau^2
+  std::vector<int32_t> q_i0;      // first angle tap of the column
+  std::vector<float> q_w;         // 4 angle tap weights of the column
+  std::vector<float> q_scale;     // X cos(psi)/a
+  FftFactors fft_t, fft_r;
+};
+
+// Validates `d` and computes the geometry.  `lds_bytes` is the per-workgroup
+// LDS the band kernels may use (it bounds the band height).  Returns
+// HRT_OK or an error with a message in `err`.
+hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
+                          std::string& err);
+
+// Algorithmic bytes of one forward / adjoint (per kernel: inputs read once,
+// outputs written once).
+double alg_bytes_forward(const Geometry& g);
+double alg_bytes_adjoint(const Geometry& g);
+// Per kernel of one direction: [0] spread+row FFT, [1] column pass,
+// [2] row inverse FFT + gather.
+void alg_bytes_kernels(const Geometry& g, bool adjoint, double out[3]);
+
+void fill_info(const Geometry& g, hrt_info* out);
+
+// Composite Gauss-Legendre rule of `order` nodes per panel on [lo, hi].
+void gauss_legendre(int order, int panels, double lo, double hi,
+                    std::vector<double>& nodes, std::vector<double>& weights);
+
+// Cubic B-spline weights of the four taps of a point whose fractional
+// lattice offset is f in [0, 1).
+void bspline_weights(double f, double w[4]);
+
+}  // namespace hrt
