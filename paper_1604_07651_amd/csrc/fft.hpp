@@ -1,11 +1,12 @@
 // Workgroup-wide mixed-radix Stockham FFTs on sequences held in LDS.
 //
 // A batch of B complex sequences of length n (n = product of the radices in
-// an FftDev) sits in LDS at buf + b*stride.  Every pass reads all of a
-// thread's butterfly inputs into registers, synchronises, then writes the
-// outputs back in place (the Stockham autosort order), so one LDS buffer is
-// enough.  Twiddles come from a table tw[j] = exp(-2 pi i j / n) computed in
-// float64 on the host and rounded once.  Forward transforms use
+// an FftDev) sits in LDS at data + b*stride.  Each pass reads one LDS buffer
+// and writes the other (Stockham autosort order), so a thread only holds the
+// R values of the butterfly it is working on.  Twiddles exp(-2 pi i m / n)
+// come from a two-level table in LDS, tw[m >> 6] * tw[nhi + (m & 63)] with
+// nhi = ceil(n / 64), each level computed in float64 on the host and rounded
+// once (about 1.5 ulp for the product).  Forward transforms use
 // exp(-2 pi i ...); INV selects exp(+2 pi i ...), unnormalised.
 #pragma once
 
@@ -13,13 +14,20 @@
 
 namespace hrt {
 
-constexpr int kMaxPassesDev = 24;
+constexpr int kMaxPassesDev = 16;
+constexpr int kTwLds = 256;  // two-level twiddle entries: n <= 64 * (256 - 64)
 
+// Length and radix sequence of one transform; the radix of pass p sits in
+// bits [4p, 4p+4) of `codes` (small enough to travel in registers).
 struct FftDev {
   int n;
   int npass;
-  int radix[kMaxPassesDev];
+  unsigned long long codes;
 };
+
+__host__ __device__ inline int fft_radix(const FftDev& f, int p) {
+  return static_cast<int>((f.codes >> (4 * p)) & 0xF);
+}
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -122,71 +130,97 @@ struct Dft<8, INV> {
   }
 };
 
-// One radix-R Stockham pass over B sequences of length n.  Ns is the length
-// of the sub-transforms already combined; CAP bounds B*n (it sizes the
-// per-thread register staging).
-template <int R, int NT, int CAP, bool INV>
-__device__ __forceinline__ void stockham_pass(float2* buf, int n, int stride,
+// floor(x / d) for 0 <= x < 2^16, 1 <= d < 2^16 by a multiply-high with
+// m = ceil(2^32 / d); m = 0 stands for d = 1 (2^32 does not fit).
+__device__ __forceinline__ int div_small(int x, unsigned m) {
+  return m ? static_cast<int>(__umulhi(static_cast<unsigned>(x), m)) : x;
+}
+__device__ __forceinline__ unsigned div_magic(int d) {
+  return d == 1 ? 0u : 0xFFFFFFFFu / static_cast<unsigned>(d) + 1u;
+}
+
+// One out-of-place radix-R Stockham pass over B sequences of length n:
+// src sequences at src + b*ss, results to dst + b*sd.  Ns is the length of
+// the sub-transforms already combined.
+template <int R, int NT, bool INV>
+__device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, int ss,
+                                              float2* __restrict__ dst, int sd, int n,
                                               int B, int Ns,
                                               const float2* __restrict__ tw) {
-  constexpr int MAXB = (CAP + R * NT - 1) / (R * NT);
   const int nb = n / R;
   const int total = B * nb;
   const int twstep = n / (Ns * R);
-  float2 v[MAXB][R];
+  const unsigned m_nb = div_magic(nb), m_ns = div_magic(Ns);
+  for (int idx = threadIdx.x; idx < total; idx += NT) {
+    const int b = div_small(idx, m_nb);
+    const int j = idx - b * nb;
+    const int k = j - div_small(j, m_ns) * Ns;
+    const float2* in = src + b * ss + j;
+    float2 v[R];
 #pragma unroll
-  for (int t = 0; t < MAXB; ++t) {
-    const int idx = static_cast<int>(threadIdx.x) + t * NT;
-    if (idx < total) {
-      const int b = idx / nb;
-      const int j = idx - b * nb;
-      const int k = j % Ns;
-      const float2* src = buf + b * stride + j;
+    for (int r = 0; r < R; ++r) v[r] = in[r * nb];
+    if (k != 0) {
+      const int nhi = (n + 63) >> 6;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[t][r] = src[r * nb];
-      if (k != 0) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          float2 w = tw[r * k * twstep];
-          if (INV) w.y = -w.y;
-          v[t][r] = cmul(v[t][r], w);
-        }
+      for (int r = 1; r < R; ++r) {
+        const int m = r * k * twstep;
+        float2 w = cmul(tw[m >> 6], tw[nhi + (m & 63)]);
+        if (INV) w.y = -w.y;
+        v[r] = cmul(v[r], w);
       }
-      Dft<R, INV>::run(v[t]);
     }
-  }
-  __syncthreads();
+    Dft<R, INV>::run(v);
+    float2* out = dst + b * sd + (j - k) * R + k;
 #pragma unroll
-  for (int t = 0; t < MAXB; ++t) {
-    const int idx = static_cast<int>(threadIdx.x) + t * NT;
-    if (idx < total) {
-      const int b = idx / nb;
-      const int j = idx - b * nb;
-      const int k = j % Ns;
-      float2* dst = buf + b * stride + (j - k) * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * Ns] = v[t][r];
-    }
-  }
-  __syncthreads();
-}
-
-// Full transform of B sequences (caller synchronises before the call).
-template <int NT, int CAP, bool INV>
-__device__ void fft_batch(float2* buf, int stride, int B, const FftDev& f,
-                          const float2* __restrict__ tw) {
-  int Ns = 1;
-  for (int p = 0; p < f.npass; ++p) {
-    const int R = f.radix[p];
-    switch (R) {
-      case 8: stockham_pass<8, NT, CAP, INV>(buf, f.n, stride, B, Ns, tw); break;
-      case 4: stockham_pass<4, NT, CAP, INV>(buf, f.n, stride, B, Ns, tw); break;
-      case 2: stockham_pass<2, NT, CAP, INV>(buf, f.n, stride, B, Ns, tw); break;
-      case 3: stockham_pass<3, NT, CAP, INV>(buf, f.n, stride, B, Ns, tw); break;
-      default: stockham_pass<5, NT, CAP, INV>(buf, f.n, stride, B, Ns, tw); break;
-    }
-    Ns *= R;
+    for (int r = 0; r < R; ++r) out[r * Ns] = v[r];
   }
 }
 
+// Transform B sequences held at data + b*stride, using `scratch` (room for
+// `group` sequences of length n) as the other half of the ping-pong; the
+// results end in place.  The caller synchronises before the call; the call
+// ends synchronised.
+template <int NT, bool INV>
+__device__ void fft_batch(float2* data, int stride, int B, float2* scratch, int group,
+                          const FftDev& f, const float2* __restrict__ tw) {
+  const int n = f.n;
+  for (int b0 = 0; b0 < B; b0 += group) {
+    const int Bg = min(group, B - b0);
+    float2* a = data + b0 * stride;
+    float2* c = scratch;
+    int sa = stride, sc = n;
+    int Ns = 1;
+    for (int p = 0; p < f.npass; ++p) {
+      switch (fft_radix(f, p)) {
+        case 8: stockham_pass<8, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
+        case 4: stockham_pass<4, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
+        case 2: stockham_pass<2, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
+        case 3: stockham_pass<3, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
+        default: stockham_pass<5, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
+      }
+      __syncthreads();
+      Ns *= fft_radix(f, p);
+      float2* t = a; a = c; c = t;
+      const int ts = sa; sa = sc; sc = ts;
+    }
+    if (a == scratch) {  // odd number of passes: copy the results back
+      for (int i = threadIdx.x; i < Bg * n; i += NT) {
+        const int b = i / n;
+        data[(b0 + b) * stride + (i - b * n)] = scratch[i];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace hrt
+
+namespace hrt {
+// Copy the two-level twiddle table (ceil(n/64) + 64 entries) into LDS.
+template <int NT>
+__device__ __forceinline__ void load_twiddles(float2* s_tw, const float2* __restrict__ tw,
+                                              int n) {
+  const int cnt = ((n + 63) >> 6) + 64;
+  for (int i = threadIdx.x; i < cnt; i += NT) s_tw[i] = tw[i];
+}
 }  // namespace hrt

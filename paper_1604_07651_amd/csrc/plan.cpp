@@ -315,18 +315,24 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
     return fail(err, HRT_ERR_GEOMETRY, "angles fall outside the log-polar lattice");
 
   // row bands: the gather kernel holds band + 3 halo rows as complex pairs
-  auto band_fits = [&](int R) {
-    const int64_t pairs = (R + 4) / 2;
-    return pairs * g.Mt * 8 <= lds_bytes && pairs * g.Mt <= kCapRow;
-  };
-  g.R = 8;
+  // row bands: the gather kernel holds band + 3 halo rows as complex pairs
+  // plus at least one sequence of FFT scratch, all in LDS
+  const int64_t seqs = lds_bytes / (static_cast<int64_t>(g.Mt) * 8);
+  auto band_fits = [&](int R) { return (R + 4) / 2 + 1 <= seqs && R <= seqs; };
+  g.R = kMaxBandRows;
   while (g.R > 2 && !band_fits(g.R)) g.R -= 2;
   if (!band_fits(g.R))
     return fail(err, HRT_ERR_UNSUPPORTED, "angle axis too long for the LDS row bands");
-  if (static_cast<int64_t>(g.Mr) * 8 > lds_bytes || g.Mr > kCapCol)
+  // spread kernel: the band's rows in 64-bit fixed point (R sequences of
+  // 8-byte cells), later the float pairs plus as much FFT scratch
+  g.grp1 = g.R / 2;
+  g.grp3 = static_cast<int>(std::min<int64_t>((g.R + 4) / 2, seqs - (g.R + 4) / 2));
+  if (2 * static_cast<int64_t>(g.Mr) * 8 > lds_bytes + 16384)
     return fail(err, HRT_ERR_UNSUPPORTED, "log-radius axis too long for an LDS column");
   g.nbands = (g.u1 - g.u0 + g.R - 1) / g.R;
 
+  if ((g.Mt + 63) / 64 + 64 > 256 || (g.Mr + 63) / 64 + 64 > 256)
+    return fail(err, HRT_ERR_UNSUPPORTED, "lattice axis above 12288 points");
   g.fft_t = factor_fft(g.Mt);
   g.fft_r = factor_fft(g.Mr);
   if (g.fft_t.npass < 0 || g.fft_r.npass < 0)

@@ -12,11 +12,9 @@
 
 namespace hrt {
 
-constexpr int kMaxPasses = 24;
-// Complex values a band kernel's batched row FFT may hold (bounds register
-// staging per thread) and the longest column FFT.
-constexpr int kCapRow = 12288;
-constexpr int kCapCol = 8192;
+constexpr int kMaxPasses = 16;
+// Tallest row band of the spread / gather kernels.
+constexpr int kMaxBandRows = 4;
 
 // Mixed-radix factorisation of an FFT length (radices 2, 3, 4, 5, 8).
 struct FftFactors {
@@ -45,6 +43,7 @@ struct Geometry {
   int ctheta = 0, crho = 0;
   int u0 = 0, u1 = 0;         // lattice rows touched by any point [u0, u1)
   int R = 0, nbands = 0;      // row band height (even) and band count
+  int grp1 = 0, grp3 = 0;     // FFT scratch (sequences) of the band kernels
   int64_t n_kept = 0;
   std::vector<int32_t> jmin;  // [nx] first kept time sample of each trace
   // Radon side, per slowness l
