@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--direct-steps", type=int, default=3)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with a plain 256 MiB device copy (reference for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the transform of a gather runs on "
@@ -173,6 +176,12 @@ def main():
                                          "plan excluded",
                                "seconds": round(cpu_sec, 2),
                                "host_cores_available": len(os.sched_getaffinity(0))}
+    if args.calib_copy:
+        a = torch.ones(64 * 1024 * 1024, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
     plan.close()
     print(json.dumps(out), flush=True)
 

@@ -271,6 +271,7 @@ struct TapAcc {
       for (int aa = 0; aa < 4; ++aa)
         atomicAdd(base + aa, to_fixed(a[bb][aa], scale));
     }
+    ix = INT_MIN;  // nothing pending
   }
 
   // add w * B3(x - xg) B3(y - yg) for the point at lattice (xg, yg)

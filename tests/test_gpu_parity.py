@@ -27,6 +27,10 @@ SMALL = {
                              nq=61, tau0=0.05, dtau=0.0045, q0=0.22, dq=0.0075,
                              oversample=2.0),
     "c2": synth.config_desc("c2"),
+    # more traces and slownesses than a band workgroup has threads
+    "wide": synth.GridDesc(nt=96, nx=1500, dt=0.004, x0=0.0, dx=4.0 / 1499, ntau=80,
+                           nq=1100, tau0=0.0, dtau=0.0048, q0=0.25,
+                           dq=(1 / 1.5 - 0.25) / 1099),
 }
 
 _cache = {}
@@ -65,7 +69,7 @@ def test_kernel_multiplier_matches_oracle(name):
     assert np.abs(K - ref).max() <= 2e-7 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("name", ["c1", "odd", "tiny", "ragged", "c2"])
+@pytest.mark.parametrize("name", ["c1", "odd", "tiny", "ragged", "wide", "c2"])
 @pytest.mark.parametrize("kind", ["random", "ricker"])
 def test_forward_and_adjoint_parity(name, kind):
     desc, plan, ora = setup(name)
@@ -101,6 +105,23 @@ def test_dot_product_float32(name):
     err = abs(lhs - rhs) / (Rf.norm().item() * G.double().norm().item())
     print(f"  dot test {name}: {err:.2e}", flush=True)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["c3"])
+def test_full_size_parity(name):
+    """The benchmark workload at full size (2048 x 1024 -> 2048 x 1024, more
+    traces and slownesses than one workgroup has threads)."""
+    desc, plan, ora = setup(name)
+    f = synth.config_gather(name)
+    print(f"[gpu] forward {name}", flush=True)
+    g = plan.forward(to_gpu(f))
+    torch.cuda.synchronize()
+    g_np = g.cpu().numpy().astype(np.float64)
+    compare(g_np, ora.forward(f), f"forward {name}")
+    print(f"[gpu] adjoint {name}", flush=True)
+    fa = plan.adjoint(g)
+    torch.cuda.synchronize()
+    compare(fa.cpu().numpy(), ora.adjoint(g_np), f"adjoint {name}")
 
 
 def test_zero_input_gives_zero_output():
