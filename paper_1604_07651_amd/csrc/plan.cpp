@@ -314,20 +314,52 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   if (xq_min < 0 || xq_max >= g.Mt)
     return fail(err, HRT_ERR_GEOMETRY, "angles fall outside the log-polar lattice");
 
-  // row bands: the gather kernel holds band + 3 halo rows as complex pairs
-  // row bands: the gather kernel holds band + 3 halo rows as complex pairs
-  // plus at least one sequence of FFT scratch, all in LDS
-  const int64_t seqs = lds_bytes / (static_cast<int64_t>(g.Mt) * 8);
-  auto band_fits = [&](int R) { return (R + 4) / 2 + 1 <= seqs && R <= seqs; };
+  // angle columns any point's taps can reach: both point sets lie within
+  // [-beta/2, beta/2]
+  {
+    const double half = 0.5 * g.beta / g.dtheta;
+    g.xw0 = std::max(0, static_cast<int>(std::floor(g.ctheta - half)) - 3);
+    const int xw1 = std::min(g.Mt, static_cast<int>(std::ceil(g.ctheta + half)) + 4);
+    g.W = xw1 - g.xw0;
+  }
+  if (xq_min < g.xw0 || xq_max >= g.xw0 + g.W)
+    return fail(err, HRT_ERR_GEOMETRY, "angles fall outside the log-polar window");
+
+  // row bands and the band kernels' LDS layout
+  const int64_t seq = static_cast<int64_t>(g.Mt) * 8;  // one complex sequence
+  auto layout = [&](int R, int grp3, bool commit) {
+    // spread: R/2 pairs, then scratch for the FFT or the fixed-point rows;
+    // the anchors go into the pairs while those are idle, else at the end
+    const int64_t d1 = (R / 2) * seq;
+    const int64_t s1 = std::max<int64_t>((R / 2) * seq, static_cast<int64_t>(R) * g.W * 8);
+    int64_t a1 = 0, b1 = d1 + s1;
+    if (kAnchorBytes > d1) { a1 = b1; b1 += kAnchorBytes; }
+    // gather: band + 3 halo rows as pairs, FFT scratch, anchors in the
+    // scratch (idle during the walk) or at the end
+    const int64_t d3 = ((R + 4) / 2) * seq;
+    const int64_t s3 = grp3 * seq;
+    int64_t a3 = d3, b3 = d3 + s3;
+    if (kAnchorBytes > s3) { a3 = b3; b3 += kAnchorBytes; }
+    if (commit) {
+      g.grp1 = R / 2;
+      g.grp3 = grp3;
+      g.k1_scratch = static_cast<int>(d1);
+      g.k1_anchor = static_cast<int>(a1);
+      g.k1_bytes = static_cast<int>(b1);
+      g.k3_scratch = static_cast<int>(d3);
+      g.k3_anchor = static_cast<int>(a3);
+      g.k3_bytes = static_cast<int>(b3);
+    }
+    return std::max(b1, b3);
+  };
   g.R = kMaxBandRows;
-  while (g.R > 2 && !band_fits(g.R)) g.R -= 2;
-  if (!band_fits(g.R))
+  while (g.R > 2 && layout(g.R, 1, false) > lds_bytes) g.R -= 2;
+  if (layout(g.R, 1, false) > lds_bytes)
     return fail(err, HRT_ERR_UNSUPPORTED, "angle axis too long for the LDS row bands");
-  // spread kernel: the band's rows in 64-bit fixed point (R sequences of
-  // 8-byte cells), later the float pairs plus as much FFT scratch
-  g.grp1 = g.R / 2;
-  g.grp3 = static_cast<int>(std::min<int64_t>((g.R + 4) / 2, seqs - (g.R + 4) / 2));
-  if (2 * static_cast<int64_t>(g.Mr) * 8 > lds_bytes + 16384)
+  int grp3 = 1;
+  while (grp3 < (g.R + 4) / 2 && layout(g.R, grp3 + 1, false) <= lds_bytes) ++grp3;
+  layout(g.R, grp3, true);
+  if (2 * static_cast<int64_t>(g.Mr) * 8 > lds_bytes + kBandStaticLds)
     return fail(err, HRT_ERR_UNSUPPORTED, "log-radius axis too long for an LDS column");
   g.nbands = (g.u1 - g.u0 + g.R - 1) / g.R;
 

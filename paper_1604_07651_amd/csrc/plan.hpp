@@ -15,6 +15,12 @@ namespace hrt {
 constexpr int kMaxPasses = 16;
 // Tallest row band of the spread / gather kernels.
 constexpr int kMaxBandRows = 4;
+// Threads of the band kernels, and the LDS their walk keeps per chunk of
+// kBandThreads units (one float64 anchor record of 48 bytes per unit).
+constexpr int kBandThreads = 512;
+constexpr int kAnchorBytes = 48 * kBandThreads;
+// Static LDS of the band kernels (walk tables, twiddles), rounded up.
+constexpr int kBandStaticLds = 8192;
 
 // Mixed-radix factorisation of an FFT length (radices 2, 3, 4, 5, 8).
 struct FftFactors {
@@ -44,6 +50,12 @@ struct Geometry {
   int u0 = 0, u1 = 0;         // lattice rows touched by any point [u0, u1)
   int R = 0, nbands = 0;      // row band height (even) and band count
   int grp1 = 0, grp3 = 0;     // FFT scratch (sequences) of the band kernels
+  int xw0 = 0, W = 0;         // angle columns [xw0, xw0 + W) points can touch
+  // dynamic LDS of the band kernels: byte offsets of the FFT scratch (the
+  // spread's fixed-point accumulator shares it) and of the walk's anchors,
+  // and the total
+  int k1_scratch = 0, k1_anchor = 0, k1_bytes = 0;
+  int k3_scratch = 0, k3_anchor = 0, k3_bytes = 0;
   int64_t n_kept = 0;
   std::vector<int32_t> jmin;  // [nx] first kept time sample of each trace
   // Radon side, per slowness l

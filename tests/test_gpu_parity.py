@@ -78,12 +78,15 @@ def test_forward_and_adjoint_parity(name, kind):
     else:
         f = synth.ricker_gather(desc, 12, 20.0, 5)
         g = ora.forward(f)
+    # outputs start as NaN: every sample must be written exactly by one band
     print(f"[gpu] forward {name} {kind}", flush=True)
-    gf = plan.forward(to_gpu(f))
+    gf = torch.full(plan.radon_shape, float("nan"), device="cuda")
+    plan.forward(to_gpu(f), out=gf)
     torch.cuda.synchronize()
     compare(gf.cpu().numpy(), ora.forward(f), f"forward {name}/{kind}")
     print(f"[gpu] adjoint {name} {kind}", flush=True)
-    fa = plan.adjoint(to_gpu(g))
+    fa = torch.full(plan.data_shape, float("nan"), device="cuda")
+    plan.adjoint(to_gpu(g), out=fa)
     torch.cuda.synchronize()
     ref = ora.adjoint(g)
     got = fa.cpu().numpy()
