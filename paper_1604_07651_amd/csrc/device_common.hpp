@@ -1,10 +1,9 @@
-// Device-side constants, the kernel parameter block and small float64 /
-// fixed-point helpers shared by the log-polar kernels.
+// Device-side constants, the kernel parameter block and the small helpers
+// shared by the log-polar kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
-#include <climits>
 #include <cstdint>
 
 #include "fft.hpp"
@@ -17,33 +16,24 @@ constexpr int kNtCol = 256;         // threads of the column kernel
 constexpr int kAbsMaxBlocks = 256;  // partial maxima of the input
 constexpr int kXcds = 8;            // MI355X: workgroups go round-robin to 8 XCDs
 
-// Everything the kernels need about one plan (passed by value).
+// Everything the lattice kernels need about one plan (passed by value).
 struct DevGeo {
-  int nt, nx, ntau, nq;
-  double dt, x0, dx, tau0, dtau, T, X;
-  double a, O1, O2, ca, sa;
-  double inv_dtheta, inv_drho, drho, ctheta, crho;
-  double wconst;  // 2 a^2 (dt/T)(dx/X): smear weight without t^, trapezoid, 1/|p|
+  int nt, nx;
   int Mt, Mr, K1, K2, u0, u1, R, nbands;
   int bands_per_xcd;  // ceil(nbands / kXcds)
   int grp1, grp3;     // FFT scratch sequences of the band kernels
   int xw0, W;         // angle columns [xw0, xw0 + W) that points can touch
-  // LDS layout of the band kernels (byte offsets into the dynamic LDS)
-  int k1_scratch, k1_anchor, k3_scratch, k3_anchor;
+  int x_frac_bits;    // fraction bits of the angle coordinate of a point entry
+  int k1_scratch, k3_scratch;   // byte offsets of the FFT scratch in the dynamic LDS
   float knorm;                  // 1/(Mt Mr): both inverse FFTs are unnormalised
-  float wmax_data, wmax_radon;  // bounds on the smear weights of the two point sets
-  const int* jmin;
-  const double* qA;
-  const double* qB;
-  const int* q_i0;
-  const float4* q_w;
-  const float* q_scale;
+  float wmax_data, wmax_radon;  // largest point weight of each point set
+  const int* jmin;              // first kept time sample of each trace
 };
 
 // Band handled by this workgroup.  Workgroup i runs on XCD i % 8; giving
-// consecutive bands to one XCD lets neighbouring bands, which read and write
-// neighbouring samples, share that XCD's L2.  Returns -1 for the few padding
-// workgroups of the last XCDs.
+// consecutive bands to one XCD lets neighbouring bands, which read
+// neighbouring samples and spectrum rows, share that XCD's L2.  Returns -1
+// for the few padding workgroups of the last XCDs.
 __device__ __forceinline__ int xcd_band(const DevGeo& G) {
   const int i = static_cast<int>(blockIdx.x);
   const int band = (i % kXcds) * G.bands_per_xcd + i / kXcds;
@@ -59,61 +49,25 @@ __device__ __forceinline__ void bspline4(float f, float w[4]) {
   w[3] = f * f * f * (1.0f / 6.0f);
 }
 
-// The point anchors move to nearby samples by small increments; the two
-// series below are exact to float64 rounding for increments up to kSeries.
-constexpr double kSeries = 0.25;
+// A point entry's coordinates: first angle tap column relative to xw0,
+// first tap row relative to the band's row n0 (rows n0 - 3 + yi .. n0 + yi),
+// and the B-spline weights of the four taps along each axis.
+struct EntryTaps {
+  int cx, cy;
+  float wx[4], wy[4];
+};
 
-// atan(z), |z| <= 0.25: Taylor series to z^31 (truncation < 1e-21 |z|).
-__device__ __forceinline__ double atan_series(double z) {
-  const double z2 = z * z;
-  double p = -1.0 / 31.0;
-#pragma unroll
-  for (int n = 14; n >= 0; --n) {
-    const double c = ((n & 1) ? -1.0 : 1.0) / (2 * n + 1);
-    p = fma(p, z2, c);
-  }
-  return z * p;
-}
-
-// 1/d for d within 15 % of 1: hardware reciprocal and two Newton steps.
-__device__ __forceinline__ double rcp_near1(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  r = fma(r, fma(-d, r, 1.0), r);
-  r = fma(r, fma(-d, r, 1.0), r);
-  return r;
-}
-
-// log(1 + x), |x| <= 0.25, as 2 atanh(y), y = x / (2 + x) (|y| < 0.12),
-// series to y^17 (truncation < 1e-19 |y|).
-__device__ __forceinline__ double log1p_series(double x) {
-  const double y = x * (0.5 * rcp_near1(1.0 + 0.5 * x));
-  const double y2 = y * y;
-  double p = 1.0 / 17.0;
-#pragma unroll
-  for (int n = 7; n >= 0; --n) p = fma(p, y2, 1.0 / (2 * n + 1));
-  return 2.0 * y * p;
-}
-
-// atan(z) for any z: halve the angle, atan(z) = 2 atan(z / (1 + sqrt(1 + z^2))),
-// until the series applies (no halving for the increments the walk meets).
-__device__ __forceinline__ double atan_any(double z) {
-  double m = 1.0;
-  while (fabs(z) > kSeries) {
-    z = z / (1.0 + sqrt(fma(z, z, 1.0)));
-    m *= 2.0;
-  }
-  return m * atan_series(z);
-}
-
-// log(1 + x) for any x > -1: halve the logarithm,
-// log1p(x) = 2 log1p(x / (1 + sqrt(1 + x))), until the series applies.
-__device__ __forceinline__ double log1p_any(double x) {
-  double m = 1.0;
-  while (fabs(x) > kSeries) {
-    x = x / (1.0 + sqrt(1.0 + x));
-    m *= 2.0;
-  }
-  return m * log1p_series(x);
+__device__ __forceinline__ EntryTaps decode_entry(uint32_t xq, uint32_t yq, int xbits) {
+  EntryTaps t;
+  const uint32_t xmask = (1u << xbits) - 1u;
+  t.cx = static_cast<int>(xq >> xbits) - 1;
+  t.cy = static_cast<int>(yq >> kYFracBits) - 3;
+  const float fx = static_cast<float>(xq & xmask) * __builtin_ldexpf(1.0f, -xbits);
+  const float fy = static_cast<float>(yq & ((1u << kYFracBits) - 1u)) *
+                   (1.0f / static_cast<float>(1u << kYFracBits));
+  bspline4(fx, t.wx);
+  bspline4(fy, t.wy);
+  return t;
 }
 
 // round(v * scale) as a 64-bit integer for |v * scale| < 2^51: adding

@@ -4,10 +4,11 @@
 // three kernels over an Mt x Mr lattice (angle theta x log radius rho) whose
 // rows [u0, u1) are all that any point touches.  Only the non-negative half
 // spectrum along theta inside the band limit L (k1 < K1) ever reaches HBM,
-// stored column-major as S[k1][row].  Point coordinates come from float64
-// anchors (eqs. transformT, transformP; the Radon side e^rho = A_l + B_l
-// tau^2); everything on the lattice is float32 with float32 accumulation,
-// except the spread, which sums in 64-bit fixed point.
+// stored column-major as S[k1][row].  Point coordinates are placed once per
+// plan in float64 on the host (eqs. transformT, transformP; the Radon side
+// e^rho = A_l + B_l tau^2) and kept on the device as per-band lists of
+// 16-byte entries; everything on the lattice is float32 with float32
+// accumulation, except the spread, which sums in 64-bit fixed point.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,10 +29,11 @@
 
 namespace hrt {
 constexpr uint64_t kMagic = 0x6872745f706c616eull;
-static_assert(kNtBand == kBandThreads, "band thread count");
-static_assert(sizeof(DataAnchors) <= kAnchorBytes && sizeof(RadonAnchors) <= kAnchorBytes,
-              "anchor records");
-static_assert(sizeof(WalkLds) + kTwLds * sizeof(float2) <= kBandStaticLds, "static LDS");
+static_assert(kTwLds * sizeof(float2) + kNtBand / 64 * sizeof(float) <= kBandStaticLds,
+              "static LDS");
+static_assert(sizeof(PointEntry) == sizeof(uint4), "point entry layout");
+// band lists: data spread, data owned, Radon spread, Radon owned
+enum { kDataSpread = 0, kDataOwn = 1, kRadonSpread = 2, kRadonOwn = 3 };
 }  // namespace hrt
 
 // ==================================================================== ABI ==
@@ -51,11 +53,8 @@ struct hrt_plan_s {
   float2* tw_t = nullptr;
   float2* tw_r = nullptr;
   int* jmin = nullptr;
-  double* qA = nullptr;
-  double* qB = nullptr;
-  int* q_i0 = nullptr;
-  float4* q_w = nullptr;
-  float* q_scale = nullptr;
+  uint4* ent[4] = {};      // band lists (kDataSpread ... kRadonOwn)
+  int64_t* off[4] = {};
   float* absmax = nullptr;  // kAbsMaxBlocks partial maxima of the current input
   size_t lds_k1 = 0, lds_k2 = 0, lds_k3 = 0;
   // per-kernel timing (hrt_profile_begin / hrt_profile_end)
@@ -126,8 +125,9 @@ hrt_status upload(T* dst, const std::vector<T>& src) {
 }
 
 void free_plan(hrt_plan_s* p) {
-  void* ptrs[] = {p->S, p->K, p->tw_t, p->tw_r, p->jmin, p->qA, p->qB,
-                  p->q_i0, p->q_w, p->q_scale, p->absmax};
+  void* ptrs[] = {p->S,      p->K,      p->tw_t,   p->tw_r,   p->jmin,  p->absmax,
+                  p->ent[0], p->ent[1], p->ent[2], p->ent[3], p->off[0], p->off[1],
+                  p->off[2], p->off[3]};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -253,7 +253,7 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
   int lds_max = 0;
   HRT_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
           "hipDeviceGetAttribute");
-  // the band kernels also hold the walk's tables and twiddles in static LDS
+  // the band kernels also hold twiddles and reduction slots in static LDS
   const int64_t lds = std::min<int64_t>(lds_max, 163840) - kBandStaticLds;
   (void)hipGetLastError();  // do not report an earlier, unrelated error
 
@@ -277,24 +277,49 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
 
   size_t total = 0;
   const std::vector<float2> twt = twiddles(g.Mt), twr = twiddles(g.Mr);
-  std::vector<float4> qw(g.d.nq);
-  for (int l = 0; l < g.d.nq; ++l)
-    qw[l] = make_float4(g.q_w[4 * l], g.q_w[4 * l + 1], g.q_w[4 * l + 2], g.q_w[4 * l + 3]);
   if ((s = dev_alloc(&p->S, static_cast<size_t>(g.K1) * g.Mr, total)) ||
       (s = dev_alloc(&p->K, static_cast<size_t>(g.K1) * g.K2, total)) ||
       (s = dev_alloc(&p->tw_t, twt.size(), total)) ||
       (s = dev_alloc(&p->tw_r, twr.size(), total)) ||
-      (s = dev_alloc(&p->jmin, g.d.nx, total)) || (s = dev_alloc(&p->qA, g.d.nq, total)) ||
-      (s = dev_alloc(&p->qB, g.d.nq, total)) || (s = dev_alloc(&p->q_i0, g.d.nq, total)) ||
-      (s = dev_alloc(&p->q_w, g.d.nq, total)) || (s = dev_alloc(&p->q_scale, g.d.nq, total)) ||
+      (s = dev_alloc(&p->jmin, g.d.nx, total)) ||
       (s = dev_alloc(&p->absmax, kAbsMaxBlocks, total)) ||
       (s = upload(p->tw_t, twt)) || (s = upload(p->tw_r, twr)) ||
-      (s = upload(p->jmin, g.jmin)) || (s = upload(p->qA, g.qA)) ||
-      (s = upload(p->qB, g.qB)) || (s = upload(p->q_i0, g.q_i0)) ||
-      (s = upload(p->q_w, qw)) || (s = upload(p->q_scale, g.q_scale))) {
+      (s = upload(p->jmin, g.jmin))) {
     free_plan(p);
     delete p;
     return s;
+  }
+  // placed points, sorted into the band lists
+  float wmax_data = 0.0f;
+  {
+    PointTables tab;
+    if ((s = build_point_tables(g, tab, err)) != HRT_OK) {
+      free_plan(p);
+      delete p;
+      return set_err(s, err);
+    }
+    for (const PointEntry& e : tab.data_spread.e) wmax_data = std::max(wmax_data, e.w);
+    const BandLists* lists[4] = {&tab.data_spread, &tab.data_own, &tab.radon_spread,
+                                 &tab.radon_own};
+    for (int i = 0; i < 4; ++i) {
+      const BandLists& L = *lists[i];
+      if ((s = dev_alloc(&p->ent[i], std::max<size_t>(1, L.e.size()), total)) ||
+          (s = dev_alloc(&p->off[i], L.off.size(), total)) ||
+          (s = upload(p->off[i], L.off))) {
+        free_plan(p);
+        delete p;
+        return s;
+      }
+      if (!L.e.empty()) {
+        hipError_t e = hipMemcpy(p->ent[i], L.e.data(), L.e.size() * sizeof(PointEntry),
+                                 hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+          free_plan(p);
+          delete p;
+          return hip_err(e, "upload point lists");
+        }
+      }
+    }
   }
   hipError_t e = hipMemset(p->S, 0, static_cast<size_t>(g.K1) * g.Mr * sizeof(float2));
   if (e != hipSuccess) {
@@ -353,30 +378,22 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
     }
   }
   DevGeo& G = p->dg;
-  G.nt = g.d.nt; G.nx = g.d.nx; G.ntau = g.d.ntau; G.nq = g.d.nq;
-  G.dt = g.d.dt; G.x0 = g.d.x0; G.dx = g.d.dx; G.tau0 = g.d.tau0; G.dtau = g.d.dtau;
-  G.T = g.T; G.X = g.X;
-  G.a = g.a; G.O1 = g.O1; G.O2 = g.O2; G.ca = g.ca; G.sa = g.sa;
-  G.inv_dtheta = 1.0 / g.dtheta; G.inv_drho = 1.0 / g.drho; G.drho = g.drho;
-  G.ctheta = g.ctheta; G.crho = g.crho;
-  G.wconst = 2.0 * g.a * g.a * (g.d.dt / g.T) * (g.d.dx / g.X);
+  G.nt = g.d.nt; G.nx = g.d.nx;
   G.Mt = g.Mt; G.Mr = g.Mr; G.K1 = g.K1; G.K2 = g.K2; G.u0 = g.u0; G.u1 = g.u1;
   G.R = g.R; G.nbands = g.nbands; G.grp1 = g.grp1; G.grp3 = g.grp3;
   G.bands_per_xcd = (g.nbands + kXcds - 1) / kXcds;
-  G.xw0 = g.xw0; G.W = g.W;
-  G.k1_scratch = g.k1_scratch; G.k1_anchor = g.k1_anchor;
-  G.k3_scratch = g.k3_scratch; G.k3_anchor = g.k3_anchor;
+  G.xw0 = g.xw0; G.W = g.W; G.x_frac_bits = g.x_frac_bits;
+  G.k1_scratch = g.k1_scratch; G.k3_scratch = g.k3_scratch;
   G.knorm = static_cast<float>(1.0 / (static_cast<double>(g.Mt) * g.Mr));
-  // |W| <= 2 a^2 dt^ dx^ / a_r (t^ <= 1, |p| >= a_r inside the trapezoid);
-  // the Radon weights are X cos(psi_l)/a; both padded by 1e-6 for rounding
-  G.wmax_data = static_cast<float>(G.wconst / g.a_r * (1.0 + 1e-6));
+  // the largest weight of each point set (the Radon weights are
+  // X cos(psi_l)/a), padded for the float32 products of the taps
+  G.wmax_data = wmax_data * (1.0f + 1e-6f);
   {
-    double m = 0.0;
-    for (float v : g.q_scale) m = std::max(m, static_cast<double>(v));
-    G.wmax_radon = static_cast<float>(m * (1.0 + 1e-6));
+    float m = 0.0f;
+    for (float v : g.q_scale) m = std::max(m, v);
+    G.wmax_radon = m * (1.0f + 1e-6f);
   }
-  G.jmin = p->jmin; G.qA = p->qA; G.qB = p->qB; G.q_i0 = p->q_i0;
-  G.q_w = p->q_w; G.q_scale = p->q_scale;
+  G.jmin = p->jmin;
   p->ft = to_dev(g.fft_t);
   p->fr = to_dev(g.fft_r);
 
@@ -440,8 +457,8 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
     {
       StageTimer t(p, st, 0);
       k_absmax<<<kAbsMaxBlocks, 256, 0, st>>>(in, static_cast<int64_t>(n_in), p->absmax);
-      k_spread_rowfft<0><<<bands, kNtBand, p->lds_k1, st>>>(p->dg, p->ft, p->tw_t, in,
-                                                            p->absmax, p->S);
+      k_spread_rowfft<0><<<bands, kNtBand, p->lds_k1, st>>>(
+          p->dg, p->ft, p->tw_t, in, p->absmax, p->ent[kDataSpread], p->off[kDataSpread], p->S);
     }
     {
       StageTimer t(p, st, 1);
@@ -449,14 +466,16 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
     }
     {
       StageTimer t(p, st, 2);
-      k_rowifft_gather<0><<<bands, kNtBand, p->lds_k3, st>>>(p->dg, p->ft, p->tw_t, p->S, out);
+      k_rowifft_gather<0><<<bands, kNtBand, p->lds_k3, st>>>(
+          p->dg, p->ft, p->tw_t, p->S, p->ent[kRadonOwn], p->off[kRadonOwn], out);
     }
   } else {
     {
       StageTimer t(p, st, 3);
       k_absmax<<<kAbsMaxBlocks, 256, 0, st>>>(in, static_cast<int64_t>(n_in), p->absmax);
-      k_spread_rowfft<1><<<bands, kNtBand, p->lds_k1, st>>>(p->dg, p->ft, p->tw_t, in,
-                                                            p->absmax, p->S);
+      k_spread_rowfft<1><<<bands, kNtBand, p->lds_k1, st>>>(
+          p->dg, p->ft, p->tw_t, in, p->absmax, p->ent[kRadonSpread], p->off[kRadonSpread],
+          p->S);
     }
     {
       StageTimer t(p, st, 4);
@@ -464,7 +483,8 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
     }
     {
       StageTimer t(p, st, 5);
-      k_rowifft_gather<1><<<bands, kNtBand, p->lds_k3, st>>>(p->dg, p->ft, p->tw_t, p->S, out);
+      k_rowifft_gather<1><<<bands, kNtBand, p->lds_k3, st>>>(
+          p->dg, p->ft, p->tw_t, p->S, p->ent[kDataOwn], p->off[kDataOwn], out);
     }
   }
   hipError_t e = hipGetLastError();

@@ -5,8 +5,9 @@
 //   k_spread_rowfft   one workgroup per band of R lattice rows: smear every
 //                     sample whose B-spline stencil reaches the band (data
 //                     samples for the forward, Radon samples for the
-//                     adjoint), then the FFT along the angle, two real rows
-//                     per complex sequence; store k1 < K1 of the half
+//                     adjoint; the band's list of placed points comes from
+//                     the plan), then the FFT along the angle, two real
+//                     rows per complex sequence; store k1 < K1 of the half
 //                     spectrum, column-major S[k1][row].
 //   k_colfft          one workgroup per kept k1: FFT along the log radius,
 //                     multiply by the kernel multiplier (its conjugate for
@@ -47,15 +48,17 @@ __global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ x, int
     partial[blockIdx.x] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
 }
 
-// MODE 0: data samples f[nx][nt] (forward); MODE 1: Radon samples g[nq][ntau]
-// (adjoint).  Dynamic LDS: the band's complex pairs at 0, the FFT scratch /
-// fixed-point accumulator at k1_scratch, the walk's anchors at k1_anchor.
+// Spread of one point set (MODE 0: data samples of f[nx][nt], forward;
+// MODE 1: Radon samples of g[nq][ntau], adjoint) from the band's list
+// ent[off[band] .. off[band+1]).  Dynamic LDS: the band's complex pairs at 0,
+// the FFT scratch at k1_scratch, which first holds the fixed-point rows.
 template <int MODE>
 __global__ __launch_bounds__(kNtBand, 4) void k_spread_rowfft(
     DevGeo G, FftDev F, const float2* __restrict__ tw, const float* __restrict__ in,
-    const float* __restrict__ absmax, float2* __restrict__ S) {
+    const float* __restrict__ absmax, const uint4* __restrict__ ent,
+    const int64_t* __restrict__ off, float2* __restrict__ S) {
   extern __shared__ float2 lds[];
-  __shared__ WalkLds walk;
+  __shared__ float s_wave[kNtBand / 64];
   __shared__ float2 s_tw[kTwLds];
   const int band = xcd_band(G);
   if (band < 0) return;
@@ -65,64 +68,45 @@ __global__ __launch_bounds__(kNtBand, 4) void k_spread_rowfft(
   const int n0 = G.u0 + band * G.R;
   const int nr = min(G.R, G.u1 - n0);
   const int npair = nr >> 1;
-  const int Mt = G.Mt;
-  const double Ylo = n0 - 2, Yhi = n0 + nr + 1;
+  const int Mt = G.Mt, W = G.W;
 
   // largest |input| (from k_absmax) fixes the fixed-point scale
   float vmax = 0.0f;
   for (int i = threadIdx.x; i < kAbsMaxBlocks; i += kNtBand) vmax = fmaxf(vmax, absmax[i]);
-  vmax = block_max(vmax, walk.wave);
+  vmax = block_max(vmax, s_wave);
   const float wmax = MODE == 0 ? G.wmax_data : G.wmax_radon;
   const bool finite = vmax <= 3.0e38f;  // false for inf and NaN
   const double scale =
       (vmax > 0.0f && finite) ? 1099511627776.0 / (static_cast<double>(wmax) * vmax) : 0.0;
-  for (int i = threadIdx.x; i < nr * G.W; i += kNtBand) acc64[i] = 0ull;
+  for (int i = threadIdx.x; i < nr * W; i += kNtBand) acc64[i] = 0ull;
   __syncthreads();
 
-  // smear every point of the band (skipped when all inputs are 0)
-  auto done = [&](TapAcc& acc) { acc.flush(acc64, G, n0, nr, scale); };
+  // smear the band's points (skipped when all inputs are 0): thread s takes
+  // a contiguous segment of the list, segments dealt lane-major so that the
+  // lanes of a wave work far apart on the lattice
   if (scale > 0.0) {
-    if (MODE == 0) {
-      DataAnchors& an = *reinterpret_cast<DataAnchors*>(base + G.k1_anchor);
-      balanced_walk<TapAcc>(
-          G.nx, walk,
-          [&](int slot, int k, int& lo, int& hi) {
-            data_range(G, k, Ylo, Yhi, lo, hi);
-            if (hi > lo) an.set(slot, G, lo, k);
-          },
-          [&](TapAcc& acc, int slot, int k, int j0, int len) {
-            for_run_values(in, static_cast<size_t>(k) * G.nt + j0, len, [&](int t, float val) {
-              if (val == 0.0f) return;
-              double xg, yg;
-              float w;
-              an.eval(slot, G, j0 + t, xg, yg, w);
-              const double fx0 = floor(xg);
-              float wx[4];
-              bspline4(static_cast<float>(xg - fx0), wx);
-              acc.add(acc64, G, n0, nr, scale, static_cast<int>(fx0) - 1, wx, yg, w * val);
-            });
-          },
-          done);
-    } else {
-      RadonAnchors& an = *reinterpret_cast<RadonAnchors*>(base + G.k1_anchor);
-      balanced_walk<TapAcc>(
-          G.nq, walk,
-          [&](int slot, int l, int& lo, int& hi) {
-            radon_range(G, G.qA[l], G.qB[l], Ylo, Yhi, lo, hi);
-            if (hi > lo) an.set(slot, G, lo, l);
-          },
-          [&](TapAcc& acc, int slot, int l, int i0, int len) {
-            const float4 q = an.qw[slot];
-            const float wx[4] = {q.x, q.y, q.z, q.w};
-            const int ix = an.i0[slot];
-            const float sc = an.sc[slot];
-            for_run_values(in, static_cast<size_t>(l) * G.ntau + i0, len, [&](int t, float val) {
-              if (val == 0.0f) return;
-              acc.add(acc64, G, n0, nr, scale, ix, wx, an.eval_y(slot, G, i0 + t), sc * val);
-            });
-          },
-          done);
+    const int64_t e0 = off[band], e1 = off[band + 1];
+    const int64_t per = (e1 - e0 + kNtBand - 1) / kNtBand;
+    const int seg = (threadIdx.x & 63) * (kNtBand / 64) + (threadIdx.x >> 6);
+    int64_t p = e0 + seg * per;
+    const int64_t pend = min(p + per, e1);
+    TapAcc acc;
+    for (; p < pend; p += 4) {
+      uint4 E[4];
+      float v[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) E[t] = (p + t < pend) ? ent[p + t] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[t] = (p + t < pend) ? in[E[t].x] : 0.0f;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (v[t] != 0.0f) {
+          const EntryTaps tp = decode_entry(E[t].y, E[t].z, G.x_frac_bits);
+          acc.add(acc64, W, nr, scale, tp, v[t] * __uint_as_float(E[t].w));
+        }
+      }
     }
+    acc.flush(acc64, W, nr, scale);
   }
   __syncthreads();
 
@@ -135,9 +119,9 @@ __global__ __launch_bounds__(kNtBand, 4) void k_spread_rowfft(
     const int m = idx - p * Mt;
     const int c = m - G.xw0;
     float lo = 0.0f, hi = 0.0f;
-    if (c >= 0 && c < G.W) {
-      lo = from_fixed(acc64[(2 * p) * G.W + c], inv);
-      hi = from_fixed(acc64[(2 * p + 1) * G.W + c], inv);
+    if (c >= 0 && c < W) {
+      lo = from_fixed(acc64[(2 * p) * W + c], inv);
+      hi = from_fixed(acc64[(2 * p + 1) * W + c], inv);
     }
     lds[idx] = make_float2(lo + bad, hi + bad);
   }
@@ -190,16 +174,16 @@ __global__ __launch_bounds__(kNtCol) void k_colfft(DevGeo G, FftDev F,
   for (int n = G.u0 + threadIdx.x; n < G.u1; n += kNtCol) col[n] = lds[n];
 }
 
-// MODE 0: gather at Radon samples into g[nq][ntau] (forward); MODE 1: gather
-// at data samples into f[nx][nt] (adjoint), zero outside the trapezoid.
-// Dynamic LDS: the band's rows plus halo as complex pairs at 0, the FFT
-// scratch at k3_scratch, the walk's anchors at k3_anchor.
+// Gather at the points the band owns (MODE 0: Radon samples into
+// g[nq][ntau], forward; MODE 1: data samples times their smear weight into
+// f[nx][nt], adjoint, zero outside the trapezoid), from the band's list
+// ent[off[band] .. off[band+1]).  Dynamic LDS: the band's rows plus halo as
+// complex pairs at 0, the FFT scratch at k3_scratch.
 template <int MODE>
 __global__ __launch_bounds__(kNtBand, 4) void k_rowifft_gather(
     DevGeo G, FftDev F, const float2* __restrict__ tw, const float2* __restrict__ S,
-    float* __restrict__ out) {
+    const uint4* __restrict__ ent, const int64_t* __restrict__ off, float* __restrict__ out) {
   extern __shared__ float2 lds[];
-  __shared__ WalkLds walk;
   __shared__ float2 s_tw[kTwLds];
   const int band = xcd_band(G);
   if (band < 0) return;
@@ -228,59 +212,16 @@ __global__ __launch_bounds__(kNtBand, 4) void k_rowifft_gather(
   __syncthreads();
   fft_batch<kNtBand, true>(lds, Mt, npair, reinterpret_cast<float2*>(base + G.k3_scratch),
                            G.grp3, F, s_tw);
-  const double Ylo = n0, Yhi = n0 + nr;
-  if (MODE == 0) {
-    RadonAnchors& an = *reinterpret_cast<RadonAnchors*>(base + G.k3_anchor);
-    balanced_walk<NoAcc>(
-        G.nq, walk,
-        [&](int slot, int l, int& lo, int& hi) {
-          radon_range(G, G.qA[l], G.qB[l], Ylo, Yhi, lo, hi);
-          if (hi > lo) an.set(slot, G, lo, l);
-        },
-        [&](NoAcc&, int slot, int l, int i0, int len) {
-          const float4 q = an.qw[slot];
-          const float wx[4] = {q.x, q.y, q.z, q.w};
-          const int ix = an.i0[slot];
-          const float sc = an.sc[slot];
-          float* orow = out + static_cast<size_t>(l) * G.ntau;
-          for (int i = i0; i < i0 + len; ++i) {
-            double yg = an.eval_y(slot, G, i);
-            if (near_row(yg)) yg = RadonAnchors::exact_y(G, i, l);
-            const double fy0 = floor(yg);
-            const int iy = static_cast<int>(fy0);
-            if (iy < n0 || iy >= n0 + nr) continue;
-            float wy[4];
-            bspline4(static_cast<float>(yg - fy0), wy);
-            orow[i] = sc * gather_taps(ldsf, Mt, L0, L1, ix, wx, iy, wy);
-          }
-        },
-        [](NoAcc&) {});
-  } else {
-    DataAnchors& an = *reinterpret_cast<DataAnchors*>(base + G.k3_anchor);
-    balanced_walk<NoAcc>(
-        G.nx, walk,
-        [&](int slot, int k, int& lo, int& hi) {
-          data_range(G, k, Ylo, Yhi, lo, hi);
-          if (hi > lo) an.set(slot, G, lo, k);
-        },
-        [&](NoAcc&, int slot, int k, int j0, int len) {
-          float* orow = out + static_cast<size_t>(k) * G.nt;
-          for (int j = j0; j < j0 + len; ++j) {
-            double xg, yg;
-            float w;
-            an.eval(slot, G, j, xg, yg, w);
-            if (near_row(yg)) DataAnchors::exact(G, j, k, xg, yg, w);
-            const double fy0 = floor(yg);
-            const int iy = static_cast<int>(fy0);
-            if (iy < n0 || iy >= n0 + nr) continue;
-            const double fx0 = floor(xg);
-            float wx[4], wy[4];
-            bspline4(static_cast<float>(xg - fx0), wx);
-            bspline4(static_cast<float>(yg - fy0), wy);
-            orow[j] = w * gather_taps(ldsf, Mt, L0, L1, static_cast<int>(fx0) - 1, wx, iy, wy);
-          }
-        },
-        [](NoAcc&) {});
+  // one point per thread, consecutive threads on consecutive entries
+  const int64_t e0 = off[band], e1 = off[band + 1];
+  const int nheld = L1 - L0, shift = n0 - L0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kNtBand) {
+    const uint4 E = ent[e];
+    const EntryTaps tp = decode_entry(E.y, E.z, G.x_frac_bits);
+    out[E.x] = __uint_as_float(E.w) *
+               gather_taps(ldsf, Mt, nheld, tp.cy + shift, G.xw0 + tp.cx, tp.wx, tp.wy);
+  }
+  if (MODE == 1) {
     // samples outside the trapezoid: each trace zeroed by one band
     for (int k = band; k < G.nx; k += G.nbands) {
       float* fk = out + static_cast<size_t>(k) * G.nt;

@@ -324,30 +324,33 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   }
   if (xq_min < g.xw0 || xq_max >= g.xw0 + g.W)
     return fail(err, HRT_ERR_GEOMETRY, "angles fall outside the log-polar window");
+  {
+    int ib = 0;
+    while ((int64_t{1} << ib) < static_cast<int64_t>(g.W) + 1) ++ib;
+    g.x_frac_bits = std::min(24, 31 - ib);
+    if (g.x_frac_bits < 16)
+      return fail(err, HRT_ERR_UNSUPPORTED, "angle window too wide for the point entries");
+  }
+  if (static_cast<int64_t>(d.nx) * d.nt >= (int64_t{1} << 31) ||
+      static_cast<int64_t>(d.nq) * d.ntau >= (int64_t{1} << 31))
+    return fail(err, HRT_ERR_UNSUPPORTED, "more than 2^31 samples in one array");
 
   // row bands and the band kernels' LDS layout
   const int64_t seq = static_cast<int64_t>(g.Mt) * 8;  // one complex sequence
   auto layout = [&](int R, int grp3, bool commit) {
-    // spread: R/2 pairs, then scratch for the FFT or the fixed-point rows;
-    // the anchors go into the pairs while those are idle, else at the end
+    // spread: R/2 complex pairs, then the FFT scratch, which holds the
+    // fixed-point rows of the accumulator before the transform
     const int64_t d1 = (R / 2) * seq;
-    const int64_t s1 = std::max<int64_t>((R / 2) * seq, static_cast<int64_t>(R) * g.W * 8);
-    int64_t a1 = 0, b1 = d1 + s1;
-    if (kAnchorBytes > d1) { a1 = b1; b1 += kAnchorBytes; }
-    // gather: band + 3 halo rows as pairs, FFT scratch, anchors in the
-    // scratch (idle during the walk) or at the end
+    const int64_t b1 = d1 + std::max<int64_t>((R / 2) * seq, static_cast<int64_t>(R) * g.W * 8);
+    // gather: band + 3 halo rows as pairs, then FFT scratch
     const int64_t d3 = ((R + 4) / 2) * seq;
-    const int64_t s3 = grp3 * seq;
-    int64_t a3 = d3, b3 = d3 + s3;
-    if (kAnchorBytes > s3) { a3 = b3; b3 += kAnchorBytes; }
+    const int64_t b3 = d3 + grp3 * seq;
     if (commit) {
       g.grp1 = R / 2;
       g.grp3 = grp3;
       g.k1_scratch = static_cast<int>(d1);
-      g.k1_anchor = static_cast<int>(a1);
       g.k1_bytes = static_cast<int>(b1);
       g.k3_scratch = static_cast<int>(d3);
-      g.k3_anchor = static_cast<int>(a3);
       g.k3_bytes = static_cast<int>(b3);
     }
     return std::max(b1, b3);
@@ -370,6 +373,143 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   if (g.fft_t.npass < 0 || g.fft_r.npass < 0)
     return fail(err, HRT_ERR_GEOMETRY, "lattice size is not 5-smooth");
   return HRT_OK;
+}
+
+namespace {
+
+// Lattice coordinates (column, row) and smear weight of data sample (j, k):
+// (t^2, x^2) -> T -> P1, W = 2 a^2 t^ e^-eta w_t w_x dt^ dx^ (eqs. f,
+// transformT, transformP; trapezoid rule in t and x).
+void place_data(const Geometry& g, int j, int k, double& xg, double& yg, double& w) {
+  const hrt_desc& d = g.d;
+  const double th = (static_cast<double>(j) * d.dt) / g.T;
+  const double xh = (d.x0 + static_cast<double>(k) * d.dx) / g.X;
+  const double ds = th * th - 0.5, dy = xh * xh - 0.5;
+  const double u = g.a * (g.ca * ds - g.sa * dy) + g.O1;
+  const double v = g.a * (g.sa * ds + g.ca * dy) + g.O2;
+  const double r2 = u * u + v * v;
+  xg = std::atan2(v, u) / g.dtheta + g.ctheta;
+  yg = 0.5 * std::log(r2) / g.drho + g.crho;
+  const double wt = (j == 0 || j == d.nt - 1) ? 0.5 : 1.0;
+  const double wx = (k == 0 || k == d.nx - 1) ? 0.5 : 1.0;
+  w = 2.0 * g.a * g.a * th * wt * wx * (d.dt / g.T) * (d.dx / g.X) / std::sqrt(r2);
+}
+
+// Row coordinate of Radon sample (i, l): e^rho = A_l + B_l tau^2 (eq. B3tauq).
+double radon_row(const Geometry& g, int i, int l) {
+  const double th = (g.d.tau0 + static_cast<double>(i) * g.d.dtau) / g.T;
+  return std::log(g.qA[l] + g.qB[l] * th * th) / g.drho + g.crho;
+}
+
+// Band lists of one point set.  `place(p, xg, yg, w)` gives the coordinates
+// of point p in [0, npts) and returns false for points outside the
+// trapezoid.  Points are placed in parallel over contiguous index ranges,
+// counted per band, then written at per-(thread, band) offsets, so every
+// list comes out in increasing index order.
+template <class PlaceF>
+hrt_status build_lists(const Geometry& g, int64_t npts, PlaceF place, BandLists& spread,
+                       BandLists& own, std::string& err) {
+  const int nb = g.nbands;
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  nth = static_cast<unsigned>(std::min<int64_t>(nth, std::max<int64_t>(1, npts / 4096)));
+  std::vector<std::vector<int64_t>> cs(nth, std::vector<int64_t>(nb, 0)), co = cs;
+  std::vector<int> bad(nth, 0);
+  const double xs = std::ldexp(1.0, g.x_frac_bits), ys = std::ldexp(1.0, kYFracBits);
+  // bands whose rows meet the stencil rows iy-1 .. iy+2, and the band of iy
+  auto bands_of = [&](int iy, int& b_lo, int& b_hi, int& b_own) {
+    b_lo = std::max(0, (iy - 1 - g.u0) / g.R);
+    b_hi = std::min(nb - 1, (iy + 2 - g.u0) / g.R);
+    b_own = (iy - g.u0) / g.R;
+  };
+  auto pass = [&](unsigned w, bool fill, std::vector<int64_t>* ps, std::vector<int64_t>* po) {
+    const int64_t p0 = npts * w / nth, p1 = npts * (w + 1) / nth;
+    for (int64_t p = p0; p < p1; ++p) {
+      double xg, yg, wt;
+      if (!place(p, xg, yg, wt)) continue;
+      const double fy = std::floor(yg);
+      const int iy = static_cast<int>(fy);
+      const double xr = xg - g.xw0;
+      if (!(iy - 1 >= g.u0 && iy + 2 < g.u1 && xr >= 1.0 && xr + 3.0 < g.W)) {
+        bad[w] = 1;
+        continue;
+      }
+      int b_lo, b_hi, b_own;
+      bands_of(iy, b_lo, b_hi, b_own);
+      const uint32_t xq = static_cast<uint32_t>(std::llround(xr * xs));
+      for (int b = b_lo; b <= b_hi; ++b) {
+        if (!fill) { ++cs[w][b]; continue; }
+        const double base = g.u0 + b * g.R - 2;
+        PointEntry e{static_cast<uint32_t>(p), xq,
+                     static_cast<uint32_t>(std::llround((yg - base) * ys)),
+                     static_cast<float>(wt)};
+        spread.e[(*ps)[b]++] = e;
+        if (b == b_own) own.e[(*po)[b]++] = e;
+      }
+      if (!fill) ++co[w][b_own];
+    }
+  };
+  auto run = [&](bool fill, std::vector<std::vector<int64_t>>* ps,
+                 std::vector<std::vector<int64_t>>* po) {
+    std::vector<std::thread> ts;
+    for (unsigned w = 1; w < nth; ++w)
+      ts.emplace_back(pass, w, fill, ps ? &(*ps)[w] : nullptr, po ? &(*po)[w] : nullptr);
+    pass(0, fill, ps ? &(*ps)[0] : nullptr, po ? &(*po)[0] : nullptr);
+    for (auto& t : ts) t.join();
+  };
+  run(false, nullptr, nullptr);
+  for (int b : bad)
+    if (b) return fail(err, HRT_ERR_GEOMETRY, "a sample falls outside the band layout");
+  // offsets: band-major, thread-minor
+  auto offsets = [&](std::vector<std::vector<int64_t>>& c, BandLists& L) {
+    L.off.assign(nb + 1, 0);
+    std::vector<std::vector<int64_t>> at(nth, std::vector<int64_t>(nb));
+    int64_t o = 0;
+    for (int b = 0; b < nb; ++b) {
+      L.off[b] = o;
+      for (unsigned w = 0; w < nth; ++w) {
+        at[w][b] = o;
+        o += c[w][b];
+      }
+    }
+    L.off[nb] = o;
+    L.e.resize(static_cast<size_t>(o));
+    return at;
+  };
+  auto ps = offsets(cs, spread);
+  auto po = offsets(co, own);
+  run(true, &ps, &po);
+  return HRT_OK;
+}
+
+}  // namespace
+
+hrt_status build_point_tables(const Geometry& g, PointTables& t, std::string& err) {
+  const hrt_desc& d = g.d;
+  hrt_status s = build_lists(
+      g, static_cast<int64_t>(d.nx) * d.nt,
+      [&](int64_t p, double& xg, double& yg, double& w) {
+        const int k = static_cast<int>(p / d.nt), j = static_cast<int>(p % d.nt);
+        if (j < g.jmin[k]) return false;
+        place_data(g, j, k, xg, yg, w);
+        return true;
+      },
+      t.data_spread, t.data_own, err);
+  if (s != HRT_OK) return s;
+  std::vector<double> qx(d.nq);
+  for (int l = 0; l < d.nq; ++l) {
+    const double qh = (d.q0 + l * d.dq) * g.X / g.T;
+    qx[l] = (g.alpha - std::atan(qh * qh)) / g.dtheta + g.ctheta;
+  }
+  return build_lists(
+      g, static_cast<int64_t>(d.nq) * d.ntau,
+      [&](int64_t p, double& xg, double& yg, double& w) {
+        const int l = static_cast<int>(p / d.ntau), i = static_cast<int>(p % d.ntau);
+        xg = qx[l];
+        yg = radon_row(g, i, l);
+        w = g.q_scale[l];
+        return true;
+      },
+      t.radon_spread, t.radon_own, err);
 }
 
 void alg_bytes_kernels(const Geometry& g, bool adjoint, double out[3]) {

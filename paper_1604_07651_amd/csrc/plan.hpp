@@ -15,12 +15,11 @@ namespace hrt {
 constexpr int kMaxPasses = 16;
 // Tallest row band of the spread / gather kernels.
 constexpr int kMaxBandRows = 4;
-// Threads of the band kernels, and the LDS their walk keeps per chunk of
-// kBandThreads units (one float64 anchor record of 48 bytes per unit).
-constexpr int kBandThreads = 512;
-constexpr int kAnchorBytes = 48 * kBandThreads;
-// Static LDS of the band kernels (walk tables, twiddles), rounded up.
-constexpr int kBandStaticLds = 8192;
+// Static LDS of the band kernels (twiddles, reduction slots), rounded up.
+constexpr int kBandStaticLds = 4096;
+// Fraction bits of the log-radius coordinate in a point entry (the integer
+// part, the row relative to the band's first tap row, needs 3 bits).
+constexpr int kYFracBits = 28;
 
 // Mixed-radix factorisation of an FFT length (radices 2, 3, 4, 5, 8).
 struct FftFactors {
@@ -51,11 +50,11 @@ struct Geometry {
   int R = 0, nbands = 0;      // row band height (even) and band count
   int grp1 = 0, grp3 = 0;     // FFT scratch (sequences) of the band kernels
   int xw0 = 0, W = 0;         // angle columns [xw0, xw0 + W) points can touch
-  // dynamic LDS of the band kernels: byte offsets of the FFT scratch (the
-  // spread's fixed-point accumulator shares it) and of the walk's anchors,
-  // and the total
-  int k1_scratch = 0, k1_anchor = 0, k1_bytes = 0;
-  int k3_scratch = 0, k3_anchor = 0, k3_bytes = 0;
+  int x_frac_bits = 0;         // fraction bits of the angle coordinate in a point entry
+  // dynamic LDS of the band kernels: byte offset of the FFT scratch (the
+  // spread's fixed-point accumulator shares it) and the total
+  int k1_scratch = 0, k1_bytes = 0;
+  int k3_scratch = 0, k3_bytes = 0;
   int64_t n_kept = 0;
   std::vector<int32_t> jmin;  // [nx] first kept time sample of each trace
   // Radon side, per slowness l
@@ -65,6 +64,38 @@ struct Geometry {
   std::vector<float> q_scale;     // X cos(psi)/a
   FftFactors fft_t, fft_r;
 };
+
+// One point of a band's list, 16 bytes: the sample's linear index in its
+// array (k*nt + j for data, l*ntau + i for Radon), its lattice coordinates
+// in fixed point relative to the band (angle: column - xw0 with
+// x_frac_bits fraction bits; log radius: row - (n0 - 2) with kYFracBits
+// fraction bits, n0 the band's first row), and its weight (the smear weight
+// of a data sample, X cos(psi)/a of a Radon sample).
+struct PointEntry {
+  uint32_t idx;
+  uint32_t xq;
+  uint32_t yq;
+  float w;
+};
+
+// Per-band point lists in one array, band b at [off[b], off[b+1]), each in
+// increasing idx order.  `spread` lists every sample whose 4x4 stencil
+// reaches a row of the band (a sample can be in two or three lists); `own`
+// lists the samples whose base row floor(row coordinate) lies in the band
+// (each sample once).
+struct BandLists {
+  std::vector<PointEntry> e;
+  std::vector<int64_t> off;
+};
+
+struct PointTables {
+  BandLists data_spread, data_own, radon_spread, radon_own;
+};
+
+// Places every kept data sample and every Radon sample on the lattice in
+// float64 (eqs. transformT, transformP, B3tx2, B3tauq) and sorts them into
+// the band lists.
+hrt_status build_point_tables(const Geometry& g, PointTables& t, std::string& err);
 
 // Validates `d` and computes the geometry.  `lds_bytes` is the per-workgroup
 // LDS the band kernels may use (it bounds the band height).  Returns
