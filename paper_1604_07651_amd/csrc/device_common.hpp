@@ -14,13 +14,11 @@ namespace hrt {
 constexpr int kNtBand = 512;        // threads of the band kernels
 constexpr int kNtCol = 256;         // threads of the column kernel
 constexpr int kAbsMaxBlocks = 256;  // partial maxima of the input
-constexpr int kXcds = 8;            // MI355X: workgroups go round-robin to 8 XCDs
 
 // Everything the lattice kernels need about one plan (passed by value).
 struct DevGeo {
   int nt, nx;
   int Mt, Mr, K1, K2, u0, u1, R, nbands;
-  int bands_per_xcd;  // ceil(nbands / kXcds)
   int grp1, grp3;     // FFT scratch sequences of the band kernels
   int xw0, W;         // angle columns [xw0, xw0 + W) that points can touch
   int x_frac_bits;    // fraction bits of the angle coordinate of a point entry
@@ -29,16 +27,6 @@ struct DevGeo {
   float wmax_data, wmax_radon;  // largest point weight of each point set
   const int* jmin;              // first kept time sample of each trace
 };
-
-// Band handled by this workgroup.  Workgroup i runs on XCD i % 8; giving
-// consecutive bands to one XCD lets neighbouring bands, which read
-// neighbouring samples and spectrum rows, share that XCD's L2.  Returns -1
-// for the few padding workgroups of the last XCDs.
-__device__ __forceinline__ int xcd_band(const DevGeo& G) {
-  const int i = static_cast<int>(blockIdx.x);
-  const int band = (i % kXcds) * G.bands_per_xcd + i / kXcds;
-  return band < G.nbands ? band : -1;
-}
 
 // Cubic B-spline weights of taps i0-1 .. i0+2 for fractional offset f.
 __device__ __forceinline__ void bspline4(float f, float w[4]) {

@@ -1,7 +1,10 @@
 // Workgroup-wide mixed-radix Stockham FFTs on sequences held in LDS.
 //
 // A batch of B complex sequences of length n (n = product of the radices in
-// an FftDev) sits in LDS at data + b*stride.  Each pass reads one LDS buffer
+// an FftDev) sits in LDS at data + b*stride.  Element e of a sequence is
+// stored at lpad(e) = e + e/16: one unused slot after every 16 elements
+// spreads the strided stores of the early passes (stride R*Ns complex
+// values) over all LDS banks.  Each pass reads one LDS buffer
 // and writes the other (Stockham autosort order), so a thread only holds the
 // R values of the butterfly it is working on.  Twiddles exp(-2 pi i m / n)
 // come from a two-level table in LDS, tw[m >> 6] * tw[nhi + (m & 63)] with
@@ -12,13 +15,15 @@
 
 #include <hip/hip_runtime.h>
 
+#include "plan.hpp"
+
 namespace hrt {
 
-constexpr int kMaxPassesDev = 16;
+
 constexpr int kTwLds = 256;  // two-level twiddle entries: n <= 64 * (256 - 64)
 
 // Length and radix sequence of one transform; the radix of pass p sits in
-// bits [4p, 4p+4) of `codes` (small enough to travel in registers).
+// bits [8p, 8p+8) of `codes` (small enough to travel in registers).
 struct FftDev {
   int n;
   int npass;
@@ -26,7 +31,7 @@ struct FftDev {
 };
 
 __host__ __device__ inline int fft_radix(const FftDev& f, int p) {
-  return static_cast<int>((f.codes >> (4 * p)) & 0xF);
+  return static_cast<int>((f.codes >> (8 * p)) & 0xFF);
 }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -130,6 +135,74 @@ struct Dft<8, INV> {
   }
 };
 
+// cos and sin of 2 pi num / den in float64 by their Taylor series after
+// reduction to [-pi, pi] (30 terms: truncation below 1e-17), for tables built
+// at compile time.
+constexpr double cx_trig2pi(int num, int den, bool sine) {
+  const double pi = 3.14159265358979323846;
+  double x = 2.0 * pi * static_cast<double>(num % den) / den;
+  if (x > pi) x -= 2.0 * pi;
+  double term = sine ? x : 1.0, sum = term;
+  for (int i = 1; i < 30; ++i) {
+    const double a = sine ? 2.0 * i : 2.0 * i - 1.0;
+    term *= -x * x / (a * (a + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+
+// exp(-2 pi i m / R) for m < R, as float.
+template <int R>
+struct RootTable {
+  float c[R], s[R];
+  constexpr RootTable() : c(), s() {
+    for (int m = 0; m < R; ++m) {
+      c[m] = static_cast<float>(cx_trig2pi(m, R, false));
+      s[m] = static_cast<float>(-cx_trig2pi(m, R, true));
+    }
+  }
+};
+
+// Composite radix R = A*B in registers (Cooley-Tukey): with n = a + A b and
+// k = B k1 + k2, X[k] = sum_a W_A^(a k1) W_R^(a k2) sum_b x[a + A b] W_B^(b k2).
+// The inner twiddles W_R^(a k2) are compile-time constants.
+template <int A, int B, bool INV>
+struct DftAB {
+  __device__ __forceinline__ static void run(float2* v) {
+    constexpr int R = A * B;
+    constexpr RootTable<R> W{};
+    float2 y[A][B];
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) y[a][b] = v[a + A * b];
+      Dft<B, INV>::run(y[a]);
+#pragma unroll
+      for (int k2 = 1; k2 < B; ++k2) {
+        if (a == 0) continue;
+        const int m = (a * k2) % R;
+        y[a][k2] = cmul(y[a][k2], make_float2(W.c[m], INV ? -W.s[m] : W.s[m]));
+      }
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) {
+      float2 z[A];
+#pragma unroll
+      for (int a = 0; a < A; ++a) z[a] = y[a][k2];
+      Dft<A, INV>::run(z);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) v[B * k1 + k2] = z[k1];
+    }
+  }
+};
+
+template <bool INV> struct Dft<6, INV> : DftAB<2, 3, INV> {};
+template <bool INV> struct Dft<9, INV> : DftAB<3, 3, INV> {};
+template <bool INV> struct Dft<10, INV> : DftAB<2, 5, INV> {};
+template <bool INV> struct Dft<12, INV> : DftAB<4, 3, INV> {};
+template <bool INV> struct Dft<15, INV> : DftAB<3, 5, INV> {};
+template <bool INV> struct Dft<16, INV> : DftAB<4, 4, INV> {};
+
 // floor(x / d) for 0 <= x < 2^16, 1 <= d < 2^16 by a multiply-high with
 // m = ceil(2^32 / d); m = 0 stands for d = 1 (2^32 does not fit).
 __device__ __forceinline__ int div_small(int x, unsigned m) {
@@ -141,44 +214,82 @@ __device__ __forceinline__ unsigned div_magic(int d) {
 
 // One out-of-place radix-R Stockham pass over B sequences of length n:
 // src sequences at src + b*ss, results to dst + b*sd.  Ns is the length of
-// the sub-transforms already combined.
+// the sub-transforms already combined.  A thread takes U butterflies at a
+// time (U*R <= 16 values in registers) and issues all their loads before any
+// arithmetic, so that the LDS latencies overlap.  The twiddles w^r of a
+// butterfly are products of the table values w^(2^i), at most four factors.
 template <int R, int NT, bool INV>
 __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, int ss,
                                               float2* __restrict__ dst, int sd, int n,
                                               int B, int Ns,
                                               const float2* __restrict__ tw) {
+  constexpr int U = R >= 16 ? 1 : (R >= 8 ? 2 : (R >= 5 ? 3 : (R >= 4 ? 4 : (R >= 3 ? 5 : 8))));
+  constexpr int NB2 = R > 8 ? 4 : (R > 4 ? 3 : (R > 2 ? 2 : 1));  // powers w^(2^i) needed
   const int nb = n / R;
   const int total = B * nb;
   const int twstep = n / (Ns * R);
+  const int nhi = (n + 63) >> 6;
   const unsigned m_nb = div_magic(nb), m_ns = div_magic(Ns);
-  for (int idx = threadIdx.x; idx < total; idx += NT) {
-    const int b = div_small(idx, m_nb);
-    const int j = idx - b * nb;
-    const int k = j - div_small(j, m_ns) * Ns;
-    const float2* in = src + b * ss + j;
-    float2 v[R];
+  for (int i0 = threadIdx.x; i0 < total; i0 += NT * U) {
+    float2 v[U][R];
+    int ob[U], oo[U], kk[U];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = in[r * nb];
-    if (k != 0) {
-      const int nhi = (n + 63) >> 6;
+    for (int u = 0; u < U; ++u) {
+      const int idx = i0 + u * NT;
+      const int b = div_small(idx, m_nb);
+      const int j = idx - b * nb;
+      const int k = j - div_small(j, m_ns) * Ns;
+      kk[u] = k;
+      ob[u] = b * sd;
+      oo[u] = (j - k) * R + k;
+      if (idx < total) {
+        const float2* in = src + b * ss;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const int m = r * k * twstep;
-        float2 w = cmul(tw[m >> 6], tw[nhi + (m & 63)]);
-        if (INV) w.y = -w.y;
-        v[r] = cmul(v[r], w);
+        for (int r = 0; r < R; ++r) v[u][r] = in[lpad(j + r * nb)];
       }
     }
-    Dft<R, INV>::run(v);
-    float2* out = dst + b * sd + (j - k) * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) out[r * Ns] = v[r];
+    for (int u = 0; u < U; ++u) {
+      if (i0 + u * NT < total) {
+        if (kk[u] != 0) {
+          float2 p2[NB2];
+#pragma unroll
+          for (int i = 0; i < NB2; ++i) {
+            const int m = (kk[u] * twstep) << i;
+            p2[i] = cmul(tw[m >> 6], tw[nhi + (m & 63)]);
+            if (INV) p2[i].y = -p2[i].y;
+          }
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            float2 w = make_float2(1.0f, 0.0f);
+            bool first = true;
+#pragma unroll
+            for (int i = 0; i < NB2; ++i) {
+              if (r & (1 << i)) {
+                w = first ? p2[i] : cmul(w, p2[i]);
+                first = false;
+              }
+            }
+            v[u][r] = cmul(v[u][r], w);
+          }
+        }
+        Dft<R, INV>::run(v[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i0 + u * NT < total) {
+        float2* out = dst + ob[u];
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[lpad(oo[u] + r * Ns)] = v[u][r];
+      }
+    }
   }
 }
 
-// Transform B sequences held at data + b*stride, using `scratch` (room for
-// `group` sequences of length n) as the other half of the ping-pong; the
-// results end in place.  The caller synchronises before the call; the call
+// Transform B sequences held at data + b*stride (padded layout), using
+// `scratch` (room for `group` padded sequences, padded_len(n) apart) as the
+// other half of the ping-pong; the results end in place.  The caller synchronises before the call; the call
 // ends synchronised.
 template <int NT, bool INV>
 __device__ void fft_batch(float2* data, int stride, int B, float2* scratch, int group,
@@ -188,15 +299,21 @@ __device__ void fft_batch(float2* data, int stride, int B, float2* scratch, int 
     const int Bg = min(group, B - b0);
     float2* a = data + b0 * stride;
     float2* c = scratch;
-    int sa = stride, sc = n;
+    int sa = stride, sc = padded_len(n);
     int Ns = 1;
     for (int p = 0; p < f.npass; ++p) {
       switch (fft_radix(f, p)) {
+        case 16: stockham_pass<16, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
+        case 15: stockham_pass<15, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
+        case 12: stockham_pass<12, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
+        case 10: stockham_pass<10, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
+        case 9: stockham_pass<9, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
         case 8: stockham_pass<8, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
+        case 6: stockham_pass<6, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
+        case 5: stockham_pass<5, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
         case 4: stockham_pass<4, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
-        case 2: stockham_pass<2, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
         case 3: stockham_pass<3, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
-        default: stockham_pass<5, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
+        default: stockham_pass<2, NT, INV>(a, sa, c, sc, n, Bg, Ns, tw); break;
       }
       __syncthreads();
       Ns *= fft_radix(f, p);
@@ -206,7 +323,8 @@ __device__ void fft_batch(float2* data, int stride, int B, float2* scratch, int 
     if (a == scratch) {  // odd number of passes: copy the results back
       for (int i = threadIdx.x; i < Bg * n; i += NT) {
         const int b = i / n;
-        data[(b0 + b) * stride + (i - b * n)] = scratch[i];
+        const int e = lpad(i - b * n);
+        data[(b0 + b) * stride + e] = scratch[b * padded_len(n) + e];
       }
       __syncthreads();
     }

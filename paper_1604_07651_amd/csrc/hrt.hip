@@ -55,6 +55,7 @@ struct hrt_plan_s {
   int* jmin = nullptr;
   uint4* ent[4] = {};      // band lists (kDataSpread ... kRadonOwn)
   int64_t* off[4] = {};
+  int* order[4] = {};      // launch order of the bands per list, longest first
   float* absmax = nullptr;  // kAbsMaxBlocks partial maxima of the current input
   size_t lds_k1 = 0, lds_k2 = 0, lds_k3 = 0;
   // per-kernel timing (hrt_profile_begin / hrt_profile_end)
@@ -88,7 +89,7 @@ FftDev to_dev(const FftFactors& f) {
   d.npass = f.npass;
   d.codes = 0;
   for (int i = 0; i < f.npass; ++i)
-    d.codes |= static_cast<unsigned long long>(f.radix[i]) << (4 * i);
+    d.codes |= static_cast<unsigned long long>(f.radix[i]) << (8 * i);
   return d;
 }
 
@@ -127,7 +128,7 @@ hrt_status upload(T* dst, const std::vector<T>& src) {
 void free_plan(hrt_plan_s* p) {
   void* ptrs[] = {p->S,      p->K,      p->tw_t,   p->tw_r,   p->jmin,  p->absmax,
                   p->ent[0], p->ent[1], p->ent[2], p->ent[3], p->off[0], p->off[1],
-                  p->off[2], p->off[3]};
+                  p->off[2], p->off[3], p->order[0], p->order[1], p->order[2], p->order[3]};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -268,7 +269,7 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
   }
   const Geometry& g = p->g;
   p->lds_k1 = static_cast<size_t>(g.k1_bytes);
-  p->lds_k2 = 2 * static_cast<size_t>(g.Mr) * sizeof(float2);
+  p->lds_k2 = 2 * static_cast<size_t>(padded_len(g.Mr)) * sizeof(float2);
   p->lds_k3 = static_cast<size_t>(g.k3_bytes);
   if (static_cast<int64_t>(p->lds_k2) > std::min<int64_t>(lds_max, 163840) - 4096) {
     delete p;
@@ -303,9 +304,16 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
                                  &tab.radon_own};
     for (int i = 0; i < 4; ++i) {
       const BandLists& L = *lists[i];
+      // longest lists first, so that the bands that start late are short
+      std::vector<int> ord(g.nbands);
+      for (int b = 0; b < g.nbands; ++b) ord[b] = b;
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+        return L.off[x + 1] - L.off[x] > L.off[y + 1] - L.off[y];
+      });
       if ((s = dev_alloc(&p->ent[i], std::max<size_t>(1, L.e.size()), total)) ||
           (s = dev_alloc(&p->off[i], L.off.size(), total)) ||
-          (s = upload(p->off[i], L.off))) {
+          (s = dev_alloc(&p->order[i], ord.size(), total)) ||
+          (s = upload(p->off[i], L.off)) || (s = upload(p->order[i], ord))) {
         free_plan(p);
         delete p;
         return s;
@@ -381,7 +389,6 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
   G.nt = g.d.nt; G.nx = g.d.nx;
   G.Mt = g.Mt; G.Mr = g.Mr; G.K1 = g.K1; G.K2 = g.K2; G.u0 = g.u0; G.u1 = g.u1;
   G.R = g.R; G.nbands = g.nbands; G.grp1 = g.grp1; G.grp3 = g.grp3;
-  G.bands_per_xcd = (g.nbands + kXcds - 1) / kXcds;
   G.xw0 = g.xw0; G.W = g.W; G.x_frac_bits = g.x_frac_bits;
   G.k1_scratch = g.k1_scratch; G.k3_scratch = g.k3_scratch;
   G.knorm = static_cast<float>(1.0 / (static_cast<double>(g.Mt) * g.Mr));
@@ -451,14 +458,14 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
   (void)hipGetLastError();  // do not report an earlier, unrelated error
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const Geometry& g = p->g;
-  // band workgroups, padded to a multiple of the XCD count (see xcd_band)
-  const dim3 bands(kXcds * ((g.nbands + kXcds - 1) / kXcds));
+  const dim3 bands(g.nbands);
   if (!adjoint) {
     {
       StageTimer t(p, st, 0);
       k_absmax<<<kAbsMaxBlocks, 256, 0, st>>>(in, static_cast<int64_t>(n_in), p->absmax);
       k_spread_rowfft<0><<<bands, kNtBand, p->lds_k1, st>>>(
-          p->dg, p->ft, p->tw_t, in, p->absmax, p->ent[kDataSpread], p->off[kDataSpread], p->S);
+          p->dg, p->ft, p->tw_t, in, p->absmax, p->ent[kDataSpread], p->off[kDataSpread],
+          p->order[kDataSpread], p->S);
     }
     {
       StageTimer t(p, st, 1);
@@ -467,7 +474,8 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
     {
       StageTimer t(p, st, 2);
       k_rowifft_gather<0><<<bands, kNtBand, p->lds_k3, st>>>(
-          p->dg, p->ft, p->tw_t, p->S, p->ent[kRadonOwn], p->off[kRadonOwn], out);
+          p->dg, p->ft, p->tw_t, p->S, p->ent[kRadonOwn], p->off[kRadonOwn], p->order[kRadonOwn],
+          out);
     }
   } else {
     {
@@ -475,7 +483,7 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
       k_absmax<<<kAbsMaxBlocks, 256, 0, st>>>(in, static_cast<int64_t>(n_in), p->absmax);
       k_spread_rowfft<1><<<bands, kNtBand, p->lds_k1, st>>>(
           p->dg, p->ft, p->tw_t, in, p->absmax, p->ent[kRadonSpread], p->off[kRadonSpread],
-          p->S);
+          p->order[kRadonSpread], p->S);
     }
     {
       StageTimer t(p, st, 4);
@@ -484,7 +492,7 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
     {
       StageTimer t(p, st, 5);
       k_rowifft_gather<1><<<bands, kNtBand, p->lds_k3, st>>>(
-          p->dg, p->ft, p->tw_t, p->S, p->ent[kDataOwn], p->off[kDataOwn], out);
+          p->dg, p->ft, p->tw_t, p->S, p->ent[kDataOwn], p->off[kDataOwn], p->order[kDataOwn], out);
     }
   }
   hipError_t e = hipGetLastError();

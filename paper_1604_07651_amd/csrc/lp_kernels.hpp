@@ -50,25 +50,25 @@ __global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ x, int
 
 // Spread of one point set (MODE 0: data samples of f[nx][nt], forward;
 // MODE 1: Radon samples of g[nq][ntau], adjoint) from the band's list
-// ent[off[band] .. off[band+1]).  Dynamic LDS: the band's complex pairs at 0,
+// ent[off[band] .. off[band+1]); workgroup i takes band order[i] (heaviest
+// lists first).  Dynamic LDS: the band's complex pairs at 0,
 // the FFT scratch at k1_scratch, which first holds the fixed-point rows.
 template <int MODE>
 __global__ __launch_bounds__(kNtBand, 4) void k_spread_rowfft(
     DevGeo G, FftDev F, const float2* __restrict__ tw, const float* __restrict__ in,
     const float* __restrict__ absmax, const uint4* __restrict__ ent,
-    const int64_t* __restrict__ off, float2* __restrict__ S) {
+    const int64_t* __restrict__ off, const int* __restrict__ order, float2* __restrict__ S) {
   extern __shared__ float2 lds[];
   __shared__ float s_wave[kNtBand / 64];
   __shared__ float2 s_tw[kTwLds];
-  const int band = xcd_band(G);
-  if (band < 0) return;
+  const int band = order[blockIdx.x];
   load_twiddles<kNtBand>(s_tw, tw, G.Mt);
   char* base = reinterpret_cast<char*>(lds);
   unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(base + G.k1_scratch);
   const int n0 = G.u0 + band * G.R;
   const int nr = min(G.R, G.u1 - n0);
   const int npair = nr >> 1;
-  const int Mt = G.Mt, W = G.W;
+  const int Mt = G.Mt, W = G.W, SP = padded_len(G.Mt);
 
   // largest |input| (from k_absmax) fixes the fixed-point scale
   float vmax = 0.0f;
@@ -123,18 +123,18 @@ __global__ __launch_bounds__(kNtBand, 4) void k_spread_rowfft(
       lo = from_fixed(acc64[(2 * p) * W + c], inv);
       hi = from_fixed(acc64[(2 * p + 1) * W + c], inv);
     }
-    lds[idx] = make_float2(lo + bad, hi + bad);
+    lds[p * SP + lpad(m)] = make_float2(lo + bad, hi + bad);
   }
   __syncthreads();
-  fft_batch<kNtBand, false>(lds, Mt, npair, reinterpret_cast<float2*>(base + G.k1_scratch),
+  fft_batch<kNtBand, false>(lds, SP, npair, reinterpret_cast<float2*>(base + G.k1_scratch),
                             G.grp1, F, s_tw);
   // two real rows per complex sequence: X1 = (Z[k] + conj Z[-k])/2,
   // X2 = (Z[k] - conj Z[-k])/(2i); keep k1 < K1
   for (int idx = threadIdx.x; idx < G.K1 * npair; idx += kNtBand) {
     const int k = idx / npair;
     const int p = idx - k * npair;
-    const float2 Z = lds[p * Mt + k];
-    const float2 Zm = lds[p * Mt + (k == 0 ? 0 : Mt - k)];
+    const float2 Z = lds[p * SP + lpad(k)];
+    const float2 Zm = lds[p * SP + lpad(k == 0 ? 0 : Mt - k)];
     const float4 o = make_float4(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y),
                                  0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
     *reinterpret_cast<float4*>(S + static_cast<size_t>(k) * G.Mr + n0 + 2 * p) = o;
@@ -150,12 +150,12 @@ __global__ __launch_bounds__(kNtCol) void k_colfft(DevGeo G, FftDev F,
   __shared__ float2 s_tw[kTwLds];
   load_twiddles<kNtCol>(s_tw, tw, G.Mr);
   const int k1 = blockIdx.x;
-  const int Mr = G.Mr;
+  const int Mr = G.Mr, SP = padded_len(G.Mr);
   float2* col = S + static_cast<size_t>(k1) * Mr;
   for (int n = threadIdx.x; n < Mr; n += kNtCol)
-    lds[n] = (n >= G.u0 && n < G.u1) ? col[n] : make_float2(0.f, 0.f);
+    lds[lpad(n)] = (n >= G.u0 && n < G.u1) ? col[n] : make_float2(0.f, 0.f);
   __syncthreads();
-  fft_batch<kNtCol, false>(lds, Mr, 1, lds + Mr, 1, F, s_tw);
+  fft_batch<kNtCol, false>(lds, SP, 1, lds + SP, 1, F, s_tw);
   const float2* Kr = K + static_cast<size_t>(k1) * G.K2;
   for (int n = threadIdx.x; n < Mr; n += kNtCol) {
     const int k = (n < Mr / 2) ? n : n - Mr;
@@ -165,28 +165,29 @@ __global__ __launch_bounds__(kNtCol) void k_colfft(DevGeo G, FftDev F,
       float2 kv = Kr[ak];
       // K(k1, -k2) = conj K(k1, k2); the adjoint uses conj K
       if ((k < 0) != ADJ) kv.y = -kv.y;
-      v = cscale(cmul(lds[n], kv), G.knorm);
+      v = cscale(cmul(lds[lpad(n)], kv), G.knorm);
     }
-    lds[n] = v;
+    lds[lpad(n)] = v;
   }
   __syncthreads();
-  fft_batch<kNtCol, true>(lds, Mr, 1, lds + Mr, 1, F, s_tw);
-  for (int n = G.u0 + threadIdx.x; n < G.u1; n += kNtCol) col[n] = lds[n];
+  fft_batch<kNtCol, true>(lds, SP, 1, lds + SP, 1, F, s_tw);
+  for (int n = G.u0 + threadIdx.x; n < G.u1; n += kNtCol) col[n] = lds[lpad(n)];
 }
 
 // Gather at the points the band owns (MODE 0: Radon samples into
 // g[nq][ntau], forward; MODE 1: data samples times their smear weight into
 // f[nx][nt], adjoint, zero outside the trapezoid), from the band's list
-// ent[off[band] .. off[band+1]).  Dynamic LDS: the band's rows plus halo as
+// ent[off[band] .. off[band+1]), workgroup i taking band order[i].  Dynamic
+// LDS: the band's rows plus halo as
 // complex pairs at 0, the FFT scratch at k3_scratch.
 template <int MODE>
 __global__ __launch_bounds__(kNtBand, 4) void k_rowifft_gather(
     DevGeo G, FftDev F, const float2* __restrict__ tw, const float2* __restrict__ S,
-    const uint4* __restrict__ ent, const int64_t* __restrict__ off, float* __restrict__ out) {
+    const uint4* __restrict__ ent, const int64_t* __restrict__ off, const int* __restrict__ order,
+    float* __restrict__ out) {
   extern __shared__ float2 lds[];
   __shared__ float2 s_tw[kTwLds];
-  const int band = xcd_band(G);
-  if (band < 0) return;
+  const int band = order[blockIdx.x];
   load_twiddles<kNtBand>(s_tw, tw, G.Mt);
   char* base = reinterpret_cast<char*>(lds);
   const float* ldsf = reinterpret_cast<const float*>(lds);
@@ -195,8 +196,8 @@ __global__ __launch_bounds__(kNtBand, 4) void k_rowifft_gather(
   const int L0 = max(G.u0, n0 - 1);
   const int L1 = min(G.u1, n0 + nr + 2);
   const int npair = (L1 - L0 + 1) >> 1;
-  const int Mt = G.Mt;
-  for (int i = threadIdx.x; i < npair * Mt; i += kNtBand) lds[i] = make_float2(0.f, 0.f);
+  const int Mt = G.Mt, SP = padded_len(G.Mt);
+  for (int i = threadIdx.x; i < npair * SP; i += kNtBand) lds[i] = make_float2(0.f, 0.f);
   __syncthreads();
   // Z = X1 + i X2 for two real rows, Hermitian completion Z[-k]
   for (int idx = threadIdx.x; idx < G.K1 * npair; idx += kNtBand) {
@@ -206,11 +207,11 @@ __global__ __launch_bounds__(kNtBand, 4) void k_rowifft_gather(
     const float2* src = S + static_cast<size_t>(k) * G.Mr;
     const float2 X1 = src[ra];
     const float2 X2 = (ra + 1 < L1) ? src[ra + 1] : make_float2(0.f, 0.f);
-    lds[p * Mt + k] = make_float2(X1.x - X2.y, X1.y + X2.x);
-    if (k > 0) lds[p * Mt + Mt - k] = make_float2(X1.x + X2.y, X2.x - X1.y);
+    lds[p * SP + lpad(k)] = make_float2(X1.x - X2.y, X1.y + X2.x);
+    if (k > 0) lds[p * SP + lpad(Mt - k)] = make_float2(X1.x + X2.y, X2.x - X1.y);
   }
   __syncthreads();
-  fft_batch<kNtBand, true>(lds, Mt, npair, reinterpret_cast<float2*>(base + G.k3_scratch),
+  fft_batch<kNtBand, true>(lds, SP, npair, reinterpret_cast<float2*>(base + G.k3_scratch),
                            G.grp3, F, s_tw);
   // one point per thread, consecutive threads on consecutive entries
   const int64_t e0 = off[band], e1 = off[band + 1];
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(kNtBand, 4) void k_rowifft_gather(
     const uint4 E = ent[e];
     const EntryTaps tp = decode_entry(E.y, E.z, G.x_frac_bits);
     out[E.x] = __uint_as_float(E.w) *
-               gather_taps(ldsf, Mt, nheld, tp.cy + shift, G.xw0 + tp.cx, tp.wx, tp.wy);
+               gather_taps(ldsf, SP, nheld, tp.cy + shift, G.xw0 + tp.cx, tp.wx, tp.wy);
   }
   if (MODE == 1) {
     // samples outside the trapezoid: each trace zeroed by one band

@@ -47,30 +47,23 @@ struct TraceScan {
 FftFactors factor_fft(int n) {
   FftFactors f;
   f.n = n;
-  int m = n, p2 = 0;
-  while (m % 2 == 0) { m /= 2; ++p2; }
-  int p3 = 0;
-  while (m % 3 == 0) { m /= 3; ++p3; }
-  int p5 = 0;
-  while (m % 5 == 0) { m /= 5; ++p5; }
-  if (m != 1) { f.npass = -1; return f; }
-  auto push = [&](int r) {
-    if (f.npass < kMaxPasses) f.radix[f.npass] = r;
-    ++f.npass;
-  };
-  // powers of two: radix 8 where possible, fours for the remainder, a
-  // single radix 2 only when p2 == 1
-  if (p2 == 1) {
-    push(2);
-  } else {
-    int r = p2 % 3;
-    int eights = (r == 1) ? (p2 - 4) / 3 : p2 / 3;
-    for (int i = 0; i < eights; ++i) push(8);
-    if (r == 1) { push(4); push(4); }
-    if (r == 2) push(4);
+  int m = n;
+  for (int p : {2, 3, 5})
+    while (m % p == 0) m /= p;
+  if (m != 1 || n < 2) { f.npass = -1; return f; }
+  // greedy: the largest supported radix that divides what is left, so that
+  // few passes (LDS round trips) remain
+  m = n;
+  while (m > 1) {
+    for (int r : kFftRadices) {
+      if (m % r == 0) {
+        if (f.npass < kMaxPasses) f.radix[f.npass] = r;
+        ++f.npass;
+        m /= r;
+        break;
+      }
+    }
   }
-  for (int i = 0; i < p3; ++i) push(3);
-  for (int i = 0; i < p5; ++i) push(5);
   if (f.npass > kMaxPasses) f.npass = -1;
   return f;
 }
@@ -336,7 +329,7 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
     return fail(err, HRT_ERR_UNSUPPORTED, "more than 2^31 samples in one array");
 
   // row bands and the band kernels' LDS layout
-  const int64_t seq = static_cast<int64_t>(g.Mt) * 8;  // one complex sequence
+  const int64_t seq = static_cast<int64_t>(padded_len(g.Mt)) * 8;  // one padded sequence
   auto layout = [&](int R, int grp3, bool commit) {
     // spread: R/2 complex pairs, then the FFT scratch, which holds the
     // fixed-point rows of the accumulator before the transform
@@ -362,7 +355,7 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   int grp3 = 1;
   while (grp3 < (g.R + 4) / 2 && layout(g.R, grp3 + 1, false) <= lds_bytes) ++grp3;
   layout(g.R, grp3, true);
-  if (2 * static_cast<int64_t>(g.Mr) * 8 > lds_bytes + kBandStaticLds)
+  if (2 * static_cast<int64_t>(padded_len(g.Mr)) * 8 > lds_bytes + kBandStaticLds)
     return fail(err, HRT_ERR_UNSUPPORTED, "log-radius axis too long for an LDS column");
   g.nbands = (g.u1 - g.u0 + g.R - 1) / g.R;
 

@@ -12,7 +12,9 @@
 
 namespace hrt {
 
-constexpr int kMaxPasses = 16;
+// FFT passes: at most 8, radices from this list, largest first.
+constexpr int kMaxPasses = 8;
+constexpr int kFftRadices[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
 // Tallest row band of the spread / gather kernels.
 constexpr int kMaxBandRows = 4;
 // Static LDS of the band kernels (twiddles, reduction slots), rounded up.
@@ -21,7 +23,14 @@ constexpr int kBandStaticLds = 4096;
 // part, the row relative to the band's first tap row, needs 3 bits).
 constexpr int kYFracBits = 28;
 
-// Mixed-radix factorisation of an FFT length (radices 2, 3, 4, 5, 8).
+// LDS layout of the FFT sequences: element e of a sequence sits at slot
+// lpad(e), and a sequence of n elements takes padded_len(n) slots.  (Padding
+// these, one unused slot per 16 elements against bank conflicts of the
+// strided passes, measured slower: the larger footprint costs occupancy.)
+constexpr int lpad(int e) { return e; }
+constexpr int padded_len(int n) { return n; }
+
+// Mixed-radix factorisation of an FFT length (radices of kFftRadices).
 struct FftFactors {
   int n = 0;
   int npass = 0;
