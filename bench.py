@@ -13,6 +13,9 @@ both directions against the FP64 oracle, and the FP64 oracle itself timed on
 the host cores.
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +27,10 @@ sys.path.insert(0, ROOT)
 METRIC = ("gathers/s fwd+adj at 2048x1024 FP32 vs GPU direct sum; "
           "rel-L2 vs FP64; HBM GB/s")
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c3_traffic.json")
+CALIB_BYTES = 256 * 1024 * 1024       # the plain device copy of --calib-copy
+STAGE_KERNELS = ["k_spread_rowfft<0>", "k_colfft<false>", "k_rowifft_gather<0>",
+                 "k_spread_rowfft<1>", "k_colfft<true>", "k_rowifft_gather<1>"]
 
 
 def log(msg):
@@ -43,6 +50,102 @@ def kernel_alg_bytes(info, desc):
             radon + spec, 2 * spec + kmul, spec + data_out]
 
 
+def kernel_source_hash():
+    """Hash of the HIP sources, to tell whether stored counters still apply."""
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_1604_07651_amd", "csrc")
+    for fn in sorted(os.listdir(src)):
+        if fn.endswith((".hpp", ".hip", ".cpp")):
+            with open(os.path.join(src, fn), "rb") as fh:
+                h.update(fn.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_kernel_name(name):
+    """'void hrt::k_colfft<false>(hrt::DevGeo, ...)' -> 'k_colfft<false>'."""
+    n = name.split("(")[0].replace("void ", "").replace("hrt::", "").strip()
+    return n
+
+
+def read_counter_csv(path):
+    """Average per dispatch of each counter, per kernel, from a rocprofv3
+    counter_collection.csv."""
+    per = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            k = short_kernel_name(row["Kernel_Name"])
+            key = (k, row["Dispatch_Id"], row["Counter_Name"])
+            per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    out = {}
+    for (k, _, c), v in per.items():
+        out.setdefault(k, {}).setdefault(c, []).append(v)
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in out.items()}, \
+        {k: {c: max(v) for c, v in d.items()} for k, d in out.items()}
+
+
+def summarize_profiles(trace_dir, fetch_dir, write_dir, commands):
+    """Turn rocprofv3 outputs (CSV) into the committed text summaries."""
+    stats = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    fetch = glob.glob(os.path.join(fetch_dir, "**", "*counter_collection.csv"), recursive=True)
+    write = glob.glob(os.path.join(write_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not (stats and fetch and write):
+        raise SystemExit("missing rocprofv3 CSV outputs")
+    rows = []
+    with open(stats[0]) as fh:
+        for row in csv.DictReader(fh):
+            rows.append((short_kernel_name(row["Name"]), int(row["Calls"]),
+                         float(row["AverageNs"]) / 1e3, float(row["Percentage"])))
+    f, fmax = read_counter_csv(fetch[0])
+    w, wmax = read_counter_csv(write[0])
+    # the calibration copy is the largest dispatch of the runtime's copy kernel
+    copy = [k for k in f if "copyBuffer" in k]
+    copy_f = max((fmax[k]["FETCH_SIZE"] for k in copy), default=None)
+    copy_w = max((wmax[k]["WRITE_SIZE"] for k in copy if k in w), default=None)
+    ff = CALIB_BYTES / (copy_f * 1024.0) if copy_f else None
+    wf = CALIB_BYTES / (copy_w * 1024.0) if copy_w else None
+    traffic = {"source_hash": kernel_source_hash(), "fetch_factor": ff, "write_factor": wf,
+               "commands": commands, "kernels": {}}
+    for k in STAGE_KERNELS:
+        if k in f and k in w:
+            traffic["kernels"][k] = {
+                "fetch_kib": f[k]["FETCH_SIZE"], "write_kib": w[k]["WRITE_SIZE"],
+                "hbm_bytes": f[k]["FETCH_SIZE"] * 1024.0 * ff + w[k]["WRITE_SIZE"] * 1024.0 * wf}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(traffic, fh, indent=1)
+    md = os.path.join(ROOT, "profiles", "c3_kernels.md")
+    with open(md, "w") as fh:
+        fh.write("# Kernel trace, C3 forward+adjoint (2048x1024 -> 2048x1024)\n\n")
+        fh.write("Commands (run from the repository root on one MI355X):\n\n")
+        for c in commands:
+            fh.write(f"    {c}\n")
+        fh.write("\n| kernel | calls | avg us | % of GPU time |\n|---|---|---|---|\n")
+        for k, n, us, pct in sorted(rows, key=lambda r: -r[3]):
+            fh.write(f"| {k} | {n} | {us:.2f} | {pct:.2f} |\n")
+        fh.write(f"\nHBM counters per dispatch (FETCH_SIZE x {ff:.3f}, WRITE_SIZE x {wf:.3f}: "
+                 f"the factors that make a plain {CALIB_BYTES >> 20} MiB device copy read and "
+                 "write its size):\n\n| kernel | FETCH KiB | WRITE KiB | HBM MB |\n|---|---|---|---|\n")
+        for k, d in traffic["kernels"].items():
+            fh.write(f"| {k} | {d['fetch_kib']:.0f} | {d['write_kib']:.0f} | "
+                     f"{d['hbm_bytes'] / 1e6:.2f} |\n")
+        fh.write(f"\nKernel source hash: {traffic['source_hash']}\n")
+    print(f"wrote {md} and {TRAFFIC_FILE}")
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counters, or None
+    if they were taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    d = t.get("kernels", {}).get(kernel)
+    return None if d is None else d["hbm_bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,7 +156,14 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (reference for "
                          "hardware byte counters)")
+    ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
+                    help="write profiles/ summaries from rocprofv3 CSV output "
+                         "directories (no GPU needed)")
+    ap.add_argument("--profile-commands", nargs="*", default=[])
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles, args.profile_commands)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the transform of a gather runs on "
               "a single device (independent gathers would shard across GPUs with "
@@ -109,6 +219,8 @@ def main():
                          "gbs": round(alg[i] / (avg_us * 1e-6) / 1e9, 1) if avg_us > 0 else None}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"])
     achieved = kernels[dom]["gbs"]
+    dom_kernel = STAGE_KERNELS[list(kernels).index(dom)]
+    traffic = stored_traffic(dom_kernel)
 
     # reference method on the GPU: direct summation over hyperbolas
     log("GPU direct summation")
@@ -144,10 +256,10 @@ def main():
                    "nt": desc.nt, "nx": desc.nx, "ntau": desc.ntau, "nq": desc.nq},
         "hbm_gbs_step": round((info["alg_bytes_fwd"] + info["alg_bytes_adj"])
                               / sec_per_step / 1e9, 1),
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": dom_kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": traffic},
         "kernels": kernels,
         "direct_sum": {"gathers_per_s": round(1.0 / direct_sec, 3),
                        "ms_fwd_adj": round(direct_sec * 1e3, 3),
@@ -158,12 +270,19 @@ def main():
         from oracle.logpolar import LogPolarOracle
         log("FP64 oracle plan (not timed)")
         ora = LogPolarOracle(desc)
-        log("FP64 oracle forward + adjoint (timed)")
+        log("FP64 oracle forward + adjoint (timed, one thread)")
+        from threadpoolctl import threadpool_limits
         g64 = g.double().cpu().numpy()
-        t0 = time.perf_counter()
-        gref = ora.forward(f64)
-        faref = ora.adjoint(g64)
-        cpu_sec = time.perf_counter() - t0
+        reps = 0
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            while True:
+                gref = ora.forward(f64)
+                faref = ora.adjoint(g64)
+                reps += 1
+                if reps >= 5 or time.perf_counter() - t0 > 10.0:
+                    break
+            cpu_sec = (time.perf_counter() - t0) / reps
         gg = g.double().cpu().numpy()
         ff = fa.double().cpu().numpy()
         out["rel_l2_vs_fp64"] = {
@@ -171,9 +290,9 @@ def main():
             "adjoint": float(np.linalg.norm(ff - faref) / np.linalg.norm(faref))}
         out["cpu_baseline"] = {"value": round(1.0 / cpu_sec, 4), "unit": "gathers/s",
                                "cores": 1, "kind": "oracle",
-                               "sample": "one full 2048x1024 gather, FP64 log-polar "
-                                         "oracle forward+adjoint (numpy, one thread), "
-                                         "plan excluded",
+                               "sample": f"{reps} x forward+adjoint of the full 2048x1024 "
+                                         "gather by the FP64 log-polar oracle (numpy, thread "
+                                         "pools limited to one thread), plan excluded",
                                "seconds": round(cpu_sec, 2),
                                "host_cores_available": len(os.sched_getaffinity(0))}
     if args.calib_copy:

@@ -81,30 +81,39 @@ __global__ __launch_bounds__(kNtBand, 4) void k_spread_rowfft(
   for (int i = threadIdx.x; i < nr * W; i += kNtBand) acc64[i] = 0ull;
   __syncthreads();
 
-  // smear the band's points (skipped when all inputs are 0): thread s takes
-  // a contiguous segment of the list, segments dealt lane-major so that the
-  // lanes of a wave work far apart on the lattice
+  // smear the band's points (skipped when all inputs are 0).  The list is
+  // read in chunks, coalesced, into the pair rows (idle until the FFT); in a
+  // chunk thread s takes a contiguous segment, segments dealt lane-major so
+  // that the lanes of a wave work far apart on the lattice.
   if (scale > 0.0) {
+    uint4* stage = reinterpret_cast<uint4*>(base);
+    const int cap = G.k1_scratch / static_cast<int>(sizeof(uint4));
     const int64_t e0 = off[band], e1 = off[band + 1];
-    const int64_t per = (e1 - e0 + kNtBand - 1) / kNtBand;
     const int seg = (threadIdx.x & 63) * (kNtBand / 64) + (threadIdx.x >> 6);
-    int64_t p = e0 + seg * per;
-    const int64_t pend = min(p + per, e1);
     TapAcc acc;
-    for (; p < pend; p += 4) {
-      uint4 E[4];
-      float v[4];
+    for (int64_t c0 = e0; c0 < e1; c0 += cap) {
+      const int n = static_cast<int>(min(static_cast<int64_t>(cap), e1 - c0));
+      for (int i = threadIdx.x; i < n; i += kNtBand) stage[i] = ent[c0 + i];
+      __syncthreads();
+      const int per = (n + kNtBand - 1) / kNtBand;
+      int p = seg * per;
+      const int pend = min(p + per, n);
+      for (; p < pend; p += 4) {
+        uint4 E[4];
+        float v[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) E[t] = (p + t < pend) ? ent[p + t] : make_uint4(0, 0, 0, 0);
+        for (int t = 0; t < 4; ++t) E[t] = (p + t < pend) ? stage[p + t] : make_uint4(0, 0, 0, 0);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) v[t] = (p + t < pend) ? in[E[t].x] : 0.0f;
+        for (int t = 0; t < 4; ++t) v[t] = (p + t < pend) ? in[E[t].x] : 0.0f;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (v[t] != 0.0f) {
-          const EntryTaps tp = decode_entry(E[t].y, E[t].z, G.x_frac_bits);
-          acc.add(acc64, W, nr, scale, tp, v[t] * __uint_as_float(E[t].w));
+        for (int t = 0; t < 4; ++t) {
+          if (v[t] != 0.0f) {
+            const EntryTaps tp = decode_entry(E[t].y, E[t].z, G.x_frac_bits);
+            acc.add(acc64, W, nr, scale, tp, v[t] * __uint_as_float(E[t].w));
+          }
         }
       }
+      __syncthreads();
     }
     acc.flush(acc64, W, nr, scale);
   }
