@@ -83,8 +83,9 @@ def read_counter_csv(path):
         {k: {c: max(v) for c, v in d.items()} for k, d in out.items()}
 
 
-def summarize_profiles(trace_dir, fetch_dir, write_dir, commands):
-    """Turn rocprofv3 outputs (CSV) into the committed text summaries."""
+def summarize_profiles(trace_dir, fetch_dir, write_dir, commands, source_hash):
+    """Turn rocprofv3 outputs (CSV) into the committed text summaries;
+    `source_hash` is the kernel_source_hash the measured runs printed."""
     stats = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
     fetch = glob.glob(os.path.join(fetch_dir, "**", "*counter_collection.csv"), recursive=True)
     write = glob.glob(os.path.join(write_dir, "**", "*counter_collection.csv"), recursive=True)
@@ -103,7 +104,7 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, commands):
     copy_w = max((wmax[k]["WRITE_SIZE"] for k in copy if k in w), default=None)
     ff = CALIB_BYTES / (copy_f * 1024.0) if copy_f else None
     wf = CALIB_BYTES / (copy_w * 1024.0) if copy_w else None
-    traffic = {"source_hash": kernel_source_hash(), "fetch_factor": ff, "write_factor": wf,
+    traffic = {"source_hash": source_hash, "fetch_factor": ff, "write_factor": wf,
                "commands": commands, "kernels": {}}
     for k in STAGE_KERNELS:
         if k in f and k in w:
@@ -160,9 +161,11 @@ def main():
                     help="write profiles/ summaries from rocprofv3 CSV output "
                          "directories (no GPU needed)")
     ap.add_argument("--profile-commands", nargs="*", default=[])
+    ap.add_argument("--profile-hash", default="",
+                    help="kernel_source_hash printed by the profiled runs")
     args = ap.parse_args()
     if args.summarize_profiles:
-        summarize_profiles(*args.summarize_profiles, args.profile_commands)
+        summarize_profiles(*args.summarize_profiles, args.profile_commands, args.profile_hash)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the transform of a gather runs on "
@@ -261,6 +264,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
         "kernels": kernels,
+        "kernel_source_hash": kernel_source_hash(),
         "direct_sum": {"gathers_per_s": round(1.0 / direct_sec, 3),
                        "ms_fwd_adj": round(direct_sec * 1e3, 3),
                        "speedup_log_polar": round(direct_sec / sec_per_step, 1)},
