@@ -11,8 +11,8 @@
 
 namespace hrt {
 
-constexpr int kNtBand = 512;        // threads of the band kernels
-constexpr int kNtCol = 256;         // threads of the column kernel
+constexpr int kNtBand = kBandThreads;  // threads of the band kernels
+constexpr int kNtCol = kColThreads;    // threads of the column kernel
 constexpr int kAbsMaxBlocks = 256;  // partial maxima of the input
 
 // Everything the lattice kernels need about one plan (passed by value).
@@ -22,9 +22,12 @@ struct DevGeo {
   int grp1, grp3;     // FFT scratch sequences of the band kernels
   int xw0, W;         // angle columns [xw0, xw0 + W) that points can touch
   int x_frac_bits;    // fraction bits of the angle coordinate of a point entry
-  int k1_scratch, k3_scratch;   // byte offsets of the FFT scratch in the dynamic LDS
+  // byte offsets in the dynamic LDS: the spread's fixed-point rows, the FFT
+  // scratch of the spread and of the gather (-1: the FFT runs in place)
+  int k1_acc, k1_scratch, k3_scratch;
+  int col_inplace;              // the column FFT runs in place
   float knorm;                  // 1/(Mt Mr): both inverse FFTs are unnormalised
-  float wmax_data, wmax_radon;  // largest point weight of each point set
+  float cmax_data, cmax_radon;  // bounds of the accumulated cells per unit input
   const int* jmin;              // first kept time sample of each trace
 };
 
@@ -58,16 +61,9 @@ __device__ __forceinline__ EntryTaps decode_entry(uint32_t xq, uint32_t yq, int 
   return t;
 }
 
-// round(v * scale) as a 64-bit integer for |v * scale| < 2^51: adding
-// 1.5 * 2^52 leaves the rounded integer in the low mantissa bits.
-__device__ __forceinline__ unsigned long long to_fixed(float v, double scale) {
-  const double d = fma(static_cast<double>(v), scale, 6755399441055744.0);
-  return static_cast<unsigned long long>(__double_as_longlong(d) - 0x4338000000000000ll);
-}
-
-// 64-bit two's complement fixed point back to float.
-__device__ __forceinline__ float from_fixed(unsigned long long q, float inv_scale) {
-  return static_cast<float>(static_cast<double>(static_cast<long long>(q))) * inv_scale;
+// LDS scratch of an FFT: null when it runs in place.
+__device__ __forceinline__ float2* fft_scratch(char* lds_base, int offset) {
+  return offset < 0 ? nullptr : reinterpret_cast<float2*>(lds_base + offset);
 }
 
 }  // namespace hrt

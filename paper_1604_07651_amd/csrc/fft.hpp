@@ -287,6 +287,108 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, in
   }
 }
 
+// In-place form of the same pass for a batch small enough that every thread
+// can hold all of its butterflies at once (U*R <= kInplaceValues; the plan
+// checks ceil(B*n/R / NT) <= kInplaceValues/R for every radix): all loads, a
+// barrier, then twiddles, DFTs and stores into the same buffer.  It needs no
+// scratch, so a workgroup takes half the LDS of the ping-pong form.
+template <int R, int NT, bool INV>
+__device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, int B, int Ns,
+                                             const float2* __restrict__ tw) {
+  constexpr int U = kInplaceValues / R;
+  constexpr int NB2 = R > 8 ? 4 : (R > 4 ? 3 : (R > 2 ? 2 : 1));
+  const int nb = n / R;
+  const int total = B * nb;
+  const int twstep = n / (Ns * R);
+  const int nhi = (n + 63) >> 6;
+  const unsigned m_nb = div_magic(nb), m_ns = div_magic(Ns);
+  float2 v[U][R];
+  int ob[U], kk[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int idx = threadIdx.x + u * NT;
+    const int b = div_small(idx, m_nb);
+    const int j = idx - b * nb;
+    const int k = j - div_small(j, m_ns) * Ns;
+    kk[u] = k;
+    ob[u] = b * stride + (j - k) * R + k;
+    if (idx < total) {
+      const float2* in = data + b * stride;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[u][r] = in[lpad(j + r * nb)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (threadIdx.x + u * NT < total) {
+      if (kk[u] != 0) {
+        float2 p2[NB2];
+#pragma unroll
+        for (int i = 0; i < NB2; ++i) {
+          const int m = (kk[u] * twstep) << i;
+          p2[i] = cmul(tw[m >> 6], tw[nhi + (m & 63)]);
+          if (INV) p2[i].y = -p2[i].y;
+        }
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = make_float2(1.0f, 0.0f);
+          bool first = true;
+#pragma unroll
+          for (int i = 0; i < NB2; ++i) {
+            if (r & (1 << i)) {
+              w = first ? p2[i] : cmul(w, p2[i]);
+              first = false;
+            }
+          }
+          v[u][r] = cmul(v[u][r], w);
+        }
+      }
+      Dft<R, INV>::run(v[u]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) data[lpad(ob[u] + r * Ns)] = v[u][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Transform B sequences at data + b*stride in place, `group` sequences at a
+// time (see inplace_pass for the size condition on a group).  The caller
+// synchronises before the call; the call ends synchronised.
+template <int NT, bool INV>
+__device__ void fft_inplace(float2* data, int stride, int B, int group, const FftDev& f,
+                            const float2* __restrict__ tw) {
+  const int n = f.n;
+  for (int b0 = 0; b0 < B; b0 += group) {
+    float2* a = data + b0 * stride;
+    const int Bg = min(group, B - b0);
+    int Ns = 1;
+    for (int p = 0; p < f.npass; ++p) {
+      switch (fft_radix(f, p)) {
+        case 16: inplace_pass<16, NT, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 15: inplace_pass<15, NT, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 12: inplace_pass<12, NT, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 10: inplace_pass<10, NT, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 9: inplace_pass<9, NT, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 8: inplace_pass<8, NT, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 6: inplace_pass<6, NT, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 5: inplace_pass<5, NT, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 4: inplace_pass<4, NT, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 3: inplace_pass<3, NT, INV>(a, stride, n, Bg, Ns, tw); break;
+        default: inplace_pass<2, NT, INV>(a, stride, n, Bg, Ns, tw); break;
+      }
+      Ns *= fft_radix(f, p);
+    }
+  }
+}
+
+// Either form: in place when `scratch` is null (`group` sequences at a time),
+// else ping-pong through `scratch` (room for `group` sequences).
+template <int NT, bool INV>
+__device__ __forceinline__ void fft_rows(float2* data, int stride, int B, float2* scratch,
+                                         int group, const FftDev& f,
+                                         const float2* __restrict__ tw);
+
 // Transform B sequences held at data + b*stride (padded layout), using
 // `scratch` (room for `group` padded sequences, padded_len(n) apart) as the
 // other half of the ping-pong; the results end in place.  The caller synchronises before the call; the call
@@ -340,5 +442,15 @@ __device__ __forceinline__ void load_twiddles(float2* s_tw, const float2* __rest
                                               int n) {
   const int cnt = ((n + 63) >> 6) + 64;
   for (int i = threadIdx.x; i < cnt; i += NT) s_tw[i] = tw[i];
+}
+}  // namespace hrt
+
+namespace hrt {
+template <int NT, bool INV>
+__device__ __forceinline__ void fft_rows(float2* data, int stride, int B, float2* scratch,
+                                         int group, const FftDev& f,
+                                         const float2* __restrict__ tw) {
+  if (scratch == nullptr) fft_inplace<NT, INV>(data, stride, B, group, f, tw);
+  else fft_batch<NT, INV>(data, stride, B, scratch, group, f, tw);
 }
 }  // namespace hrt

@@ -269,7 +269,7 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
   }
   const Geometry& g = p->g;
   p->lds_k1 = static_cast<size_t>(g.k1_bytes);
-  p->lds_k2 = 2 * static_cast<size_t>(padded_len(g.Mr)) * sizeof(float2);
+  p->lds_k2 = static_cast<size_t>(g.col_bytes);
   p->lds_k3 = static_cast<size_t>(g.k3_bytes);
   if (static_cast<int64_t>(p->lds_k2) > std::min<int64_t>(lds_max, 163840) - 4096) {
     delete p;
@@ -291,7 +291,7 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
     return s;
   }
   // placed points, sorted into the band lists
-  float wmax_data = 0.0f;
+  float cmax_data = 0.0f, cmax_radon = 0.0f;
   {
     PointTables tab;
     if ((s = build_point_tables(g, tab, err)) != HRT_OK) {
@@ -299,7 +299,9 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
       delete p;
       return set_err(s, err);
     }
-    for (const PointEntry& e : tab.data_spread.e) wmax_data = std::max(wmax_data, e.w);
+    // padded for the float32 rounding of the taps
+    cmax_data = static_cast<float>(tab.cmax_data * (1.0 + 1e-5));
+    cmax_radon = static_cast<float>(tab.cmax_radon * (1.0 + 1e-5));
     const BandLists* lists[4] = {&tab.data_spread, &tab.data_own, &tab.radon_spread,
                                  &tab.radon_own};
     for (int i = 0; i < 4; ++i) {
@@ -390,16 +392,11 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
   G.Mt = g.Mt; G.Mr = g.Mr; G.K1 = g.K1; G.K2 = g.K2; G.u0 = g.u0; G.u1 = g.u1;
   G.R = g.R; G.nbands = g.nbands; G.grp1 = g.grp1; G.grp3 = g.grp3;
   G.xw0 = g.xw0; G.W = g.W; G.x_frac_bits = g.x_frac_bits;
-  G.k1_scratch = g.k1_scratch; G.k3_scratch = g.k3_scratch;
+  G.k1_acc = g.k1_acc; G.k1_scratch = g.k1_scratch; G.k3_scratch = g.k3_scratch;
+  G.col_inplace = g.inplace_col ? 1 : 0;
   G.knorm = static_cast<float>(1.0 / (static_cast<double>(g.Mt) * g.Mr));
-  // the largest weight of each point set (the Radon weights are
-  // X cos(psi_l)/a), padded for the float32 products of the taps
-  G.wmax_data = wmax_data * (1.0f + 1e-6f);
-  {
-    float m = 0.0f;
-    for (float v : g.q_scale) m = std::max(m, v);
-    G.wmax_radon = m * (1.0f + 1e-6f);
-  }
+  G.cmax_data = cmax_data;
+  G.cmax_radon = cmax_radon;
   G.jmin = p->jmin;
   p->ft = to_dev(g.fft_t);
   p->fr = to_dev(g.fft_r);

@@ -51,8 +51,9 @@ __global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ x, int
 // Spread of one point set (MODE 0: data samples of f[nx][nt], forward;
 // MODE 1: Radon samples of g[nq][ntau], adjoint) from the band's list
 // ent[off[band] .. off[band+1]); workgroup i takes band order[i] (heaviest
-// lists first).  Dynamic LDS: the band's complex pairs at 0,
-// the FFT scratch at k1_scratch, which first holds the fixed-point rows.
+// lists first).  Dynamic LDS: the band's complex pairs at 0 (they first
+// stage the point list), the 32-bit fixed-point rows at k1_acc, the FFT
+// scratch (if any) at k1_scratch over the fixed-point rows.
 template <int MODE>
 __global__ __launch_bounds__(kNtBand, 4) void k_spread_rowfft(
     DevGeo G, FftDev F, const float2* __restrict__ tw, const float* __restrict__ in,
@@ -64,33 +65,32 @@ __global__ __launch_bounds__(kNtBand, 4) void k_spread_rowfft(
   const int band = order[blockIdx.x];
   load_twiddles<kNtBand>(s_tw, tw, G.Mt);
   char* base = reinterpret_cast<char*>(lds);
-  unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(base + G.k1_scratch);
+  int* acc = reinterpret_cast<int*>(base + G.k1_acc);
   const int n0 = G.u0 + band * G.R;
   const int nr = min(G.R, G.u1 - n0);
   const int npair = nr >> 1;
   const int Mt = G.Mt, W = G.W, SP = padded_len(G.Mt);
 
-  // largest |input| (from k_absmax) fixes the fixed-point scale
+  // largest |input| (from k_absmax) fixes the fixed-point scale: every
+  // cell stays within 2^30 (cmax bounds a cell per unit input)
   float vmax = 0.0f;
   for (int i = threadIdx.x; i < kAbsMaxBlocks; i += kNtBand) vmax = fmaxf(vmax, absmax[i]);
   vmax = block_max(vmax, s_wave);
-  const float wmax = MODE == 0 ? G.wmax_data : G.wmax_radon;
+  const float cmax = MODE == 0 ? G.cmax_data : G.cmax_radon;
   const bool finite = vmax <= 3.0e38f;  // false for inf and NaN
-  const double scale =
-      (vmax > 0.0f && finite) ? 1099511627776.0 / (static_cast<double>(wmax) * vmax) : 0.0;
-  for (int i = threadIdx.x; i < nr * W; i += kNtBand) acc64[i] = 0ull;
+  const float scale = (vmax > 0.0f && finite) ? 1073741824.0f / (cmax * vmax) : 0.0f;
+  for (int i = threadIdx.x; i < nr * W; i += kNtBand) acc[i] = 0;
   __syncthreads();
 
   // smear the band's points (skipped when all inputs are 0).  The list is
   // read in chunks, coalesced, into the pair rows (idle until the FFT); in a
   // chunk thread s takes a contiguous segment, segments dealt lane-major so
   // that the lanes of a wave work far apart on the lattice.
-  if (scale > 0.0) {
+  if (scale > 0.0f) {
     uint4* stage = reinterpret_cast<uint4*>(base);
-    const int cap = G.k1_scratch / static_cast<int>(sizeof(uint4));
+    const int cap = G.k1_acc / static_cast<int>(sizeof(uint4));
     const int64_t e0 = off[band], e1 = off[band + 1];
     const int seg = (threadIdx.x & 63) * (kNtBand / 64) + (threadIdx.x >> 6);
-    TapAcc acc;
     for (int64_t c0 = e0; c0 < e1; c0 += cap) {
       const int n = static_cast<int>(min(static_cast<int64_t>(cap), e1 - c0));
       for (int i = threadIdx.x; i < n; i += kNtBand) stage[i] = ent[c0 + i];
@@ -109,19 +109,18 @@ __global__ __launch_bounds__(kNtBand, 4) void k_spread_rowfft(
         for (int t = 0; t < 4; ++t) {
           if (v[t] != 0.0f) {
             const EntryTaps tp = decode_entry(E[t].y, E[t].z, G.x_frac_bits);
-            acc.add(acc64, W, nr, scale, tp, v[t] * __uint_as_float(E[t].w));
+            spread_taps(acc, W, nr, tp, v[t] * __uint_as_float(E[t].w) * scale);
           }
         }
       }
       __syncthreads();
     }
-    acc.flush(acc64, W, nr, scale);
   }
   __syncthreads();
 
   // fixed point -> float, rows (2p, 2p+1) into complex pair p (zero outside
   // the columns points can reach)
-  const float inv = scale > 0.0 ? static_cast<float>(1.0 / scale) : 0.0f;
+  const float inv = scale > 0.0f ? 1.0f / scale : 0.0f;
   const float bad = finite ? 0.0f : __int_as_float(0x7fc00000);
   for (int idx = threadIdx.x; idx < npair * Mt; idx += kNtBand) {
     const int p = idx / Mt;
@@ -129,14 +128,13 @@ __global__ __launch_bounds__(kNtBand, 4) void k_spread_rowfft(
     const int c = m - G.xw0;
     float lo = 0.0f, hi = 0.0f;
     if (c >= 0 && c < W) {
-      lo = from_fixed(acc64[(2 * p) * W + c], inv);
-      hi = from_fixed(acc64[(2 * p + 1) * W + c], inv);
+      lo = static_cast<float>(acc[(2 * p) * W + c]) * inv;
+      hi = static_cast<float>(acc[(2 * p + 1) * W + c]) * inv;
     }
     lds[p * SP + lpad(m)] = make_float2(lo + bad, hi + bad);
   }
   __syncthreads();
-  fft_batch<kNtBand, false>(lds, SP, npair, reinterpret_cast<float2*>(base + G.k1_scratch),
-                            G.grp1, F, s_tw);
+  fft_rows<kNtBand, false>(lds, SP, npair, fft_scratch(base, G.k1_scratch), G.grp1, F, s_tw);
   // two real rows per complex sequence: X1 = (Z[k] + conj Z[-k])/2,
   // X2 = (Z[k] - conj Z[-k])/(2i); keep k1 < K1
   for (int idx = threadIdx.x; idx < G.K1 * npair; idx += kNtBand) {
@@ -164,7 +162,8 @@ __global__ __launch_bounds__(kNtCol) void k_colfft(DevGeo G, FftDev F,
   for (int n = threadIdx.x; n < Mr; n += kNtCol)
     lds[lpad(n)] = (n >= G.u0 && n < G.u1) ? col[n] : make_float2(0.f, 0.f);
   __syncthreads();
-  fft_batch<kNtCol, false>(lds, SP, 1, lds + SP, 1, F, s_tw);
+  float2* cscr = G.col_inplace ? nullptr : lds + SP;
+  fft_rows<kNtCol, false>(lds, SP, 1, cscr, 1, F, s_tw);
   const float2* Kr = K + static_cast<size_t>(k1) * G.K2;
   for (int n = threadIdx.x; n < Mr; n += kNtCol) {
     const int k = (n < Mr / 2) ? n : n - Mr;
@@ -179,7 +178,7 @@ __global__ __launch_bounds__(kNtCol) void k_colfft(DevGeo G, FftDev F,
     lds[lpad(n)] = v;
   }
   __syncthreads();
-  fft_batch<kNtCol, true>(lds, SP, 1, lds + SP, 1, F, s_tw);
+  fft_rows<kNtCol, true>(lds, SP, 1, cscr, 1, F, s_tw);
   for (int n = G.u0 + threadIdx.x; n < G.u1; n += kNtCol) col[n] = lds[lpad(n)];
 }
 
@@ -188,7 +187,7 @@ __global__ __launch_bounds__(kNtCol) void k_colfft(DevGeo G, FftDev F,
 // f[nx][nt], adjoint, zero outside the trapezoid), from the band's list
 // ent[off[band] .. off[band+1]), workgroup i taking band order[i].  Dynamic
 // LDS: the band's rows plus halo as
-// complex pairs at 0, the FFT scratch at k3_scratch.
+// complex pairs at 0, the FFT scratch (if any) at k3_scratch.
 template <int MODE>
 __global__ __launch_bounds__(kNtBand, 4) void k_rowifft_gather(
     DevGeo G, FftDev F, const float2* __restrict__ tw, const float2* __restrict__ S,
@@ -220,8 +219,7 @@ __global__ __launch_bounds__(kNtBand, 4) void k_rowifft_gather(
     if (k > 0) lds[p * SP + lpad(Mt - k)] = make_float2(X1.x + X2.y, X2.x - X1.y);
   }
   __syncthreads();
-  fft_batch<kNtBand, true>(lds, SP, npair, reinterpret_cast<float2*>(base + G.k3_scratch),
-                           G.grp3, F, s_tw);
+  fft_rows<kNtBand, true>(lds, SP, npair, fft_scratch(base, G.k3_scratch), G.grp3, F, s_tw);
   // one point per thread, consecutive threads on consecutive entries
   const int64_t e0 = off[band], e1 = off[band + 1];
   const int nheld = L1 - L0, shift = n0 - L0;

@@ -44,6 +44,16 @@ struct TraceScan {
 
 }  // namespace
 
+bool fft_fits_inplace(const FftFactors& f, int batch, int threads) {
+  if (f.npass < 1) return false;
+  for (int p = 0; p < f.npass; ++p) {
+    const int64_t r = f.radix[p];
+    const int64_t bfly = static_cast<int64_t>(batch) * f.n / r;
+    if ((bfly + threads - 1) / threads > kInplaceValues / r) return false;
+  }
+  return true;
+}
+
 FftFactors factor_fft(int n) {
   FftFactors f;
   f.n = n;
@@ -328,22 +338,44 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
       static_cast<int64_t>(d.nq) * d.ntau >= (int64_t{1} << 31))
     return fail(err, HRT_ERR_UNSUPPORTED, "more than 2^31 samples in one array");
 
+  // FFT factorisations (needed by the LDS layout)
+  if ((g.Mt + 63) / 64 + 64 > 256 || (g.Mr + 63) / 64 + 64 > 256)
+    return fail(err, HRT_ERR_UNSUPPORTED, "lattice axis above 12288 points");
+  g.fft_t = factor_fft(g.Mt);
+  g.fft_r = factor_fft(g.Mr);
+  if (g.fft_t.npass < 0 || g.fft_r.npass < 0)
+    return fail(err, HRT_ERR_GEOMETRY, "lattice size is not 5-smooth");
+
   // row bands and the band kernels' LDS layout
   const int64_t seq = static_cast<int64_t>(padded_len(g.Mt)) * 8;  // one padded sequence
+  // largest group of sequences the in-place FFT takes at once (0: none)
+  auto inplace_group = [&](int B) {
+    int grp = 0;
+    for (int b = 1; b <= B; ++b)
+      if (fft_fits_inplace(g.fft_t, b, kBandThreads)) grp = b;
+    return grp;
+  };
   auto layout = [&](int R, int grp3, bool commit) {
-    // spread: R/2 complex pairs, then the FFT scratch, which holds the
-    // fixed-point rows of the accumulator before the transform
+    // spread: R/2 complex pairs (they also stage the point list), then the
+    // 32-bit fixed-point rows, which the FFT scratch reuses when the FFT
+    // does not run in place
+    const int in1 = inplace_group(R / 2);
     const int64_t d1 = (R / 2) * seq;
-    const int64_t b1 = d1 + std::max<int64_t>((R / 2) * seq, static_cast<int64_t>(R) * g.W * 8);
-    // gather: band + 3 halo rows as pairs, then FFT scratch
+    const int64_t acc = static_cast<int64_t>(R) * g.W * 4;
+    const int64_t b1 = d1 + std::max<int64_t>(acc, in1 ? 0 : (R / 2) * seq);
+    // gather: band + 3 halo rows as pairs, then the FFT scratch if needed
+    const int in3 = inplace_group((R + 4) / 2);
     const int64_t d3 = ((R + 4) / 2) * seq;
-    const int64_t b3 = d3 + grp3 * seq;
+    const int64_t b3 = d3 + (in3 ? 0 : grp3 * seq);
     if (commit) {
-      g.grp1 = R / 2;
-      g.grp3 = grp3;
-      g.k1_scratch = static_cast<int>(d1);
+      g.inplace1 = in1 > 0;
+      g.inplace3 = in3 > 0;
+      g.grp1 = in1 ? in1 : R / 2;
+      g.grp3 = in3 ? in3 : grp3;
+      g.k1_acc = static_cast<int>(d1);
+      g.k1_scratch = in1 ? -1 : static_cast<int>(d1);
       g.k1_bytes = static_cast<int>(b1);
-      g.k3_scratch = static_cast<int>(d3);
+      g.k3_scratch = in3 ? -1 : static_cast<int>(d3);
       g.k3_bytes = static_cast<int>(b3);
     }
     return std::max(b1, b3);
@@ -355,16 +387,12 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   int grp3 = 1;
   while (grp3 < (g.R + 4) / 2 && layout(g.R, grp3 + 1, false) <= lds_bytes) ++grp3;
   layout(g.R, grp3, true);
-  if (2 * static_cast<int64_t>(padded_len(g.Mr)) * 8 > lds_bytes + kBandStaticLds)
+  g.inplace_col = fft_fits_inplace(g.fft_r, 1, kColThreads);
+  g.col_bytes = (g.inplace_col ? 1 : 2) * padded_len(g.Mr) * 8;
+  if (g.col_bytes > lds_bytes + kBandStaticLds)
     return fail(err, HRT_ERR_UNSUPPORTED, "log-radius axis too long for an LDS column");
   g.nbands = (g.u1 - g.u0 + g.R - 1) / g.R;
 
-  if ((g.Mt + 63) / 64 + 64 > 256 || (g.Mr + 63) / 64 + 64 > 256)
-    return fail(err, HRT_ERR_UNSUPPORTED, "lattice axis above 12288 points");
-  g.fft_t = factor_fft(g.Mt);
-  g.fft_r = factor_fft(g.Mr);
-  if (g.fft_t.npass < 0 || g.fft_r.npass < 0)
-    return fail(err, HRT_ERR_GEOMETRY, "lattice size is not 5-smooth");
   return HRT_OK;
 }
 
@@ -474,6 +502,46 @@ hrt_status build_lists(const Geometry& g, int64_t npts, PlaceF place, BandLists&
   return HRT_OK;
 }
 
+// Largest over the cells of any band of the sum of |w| x B3 x B3 of the
+// entries of a spread list, with the coordinates decoded as the kernels
+// decode them.
+double list_cmax(const Geometry& g, const BandLists& L) {
+  const int nb = g.nbands;
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  nth = std::min<unsigned>(nth, static_cast<unsigned>(nb));
+  std::vector<double> best(nth, 0.0);
+  auto work = [&](unsigned w) {
+    std::vector<double> cell;
+    for (int b = static_cast<int>(w); b < nb; b += static_cast<int>(nth)) {
+      const int n0 = g.u0 + b * g.R;
+      const int nr = std::min(g.R, g.u1 - n0);
+      cell.assign(static_cast<size_t>(nr) * g.W, 0.0);
+      for (int64_t i = L.off[b]; i < L.off[b + 1]; ++i) {
+        const PointEntry& e = L.e[i];
+        const double x = std::ldexp(static_cast<double>(e.xq), -g.x_frac_bits);
+        const double y = std::ldexp(static_cast<double>(e.yq), -kYFracBits);
+        const double fx = std::floor(x), fy = std::floor(y);
+        const int cx = static_cast<int>(fx) - 1, cy = static_cast<int>(fy) - 3;
+        double wx[4], wy[4];
+        bspline_weights(x - fx, wx);
+        bspline_weights(y - fy, wy);
+        for (int bb = 0; bb < 4; ++bb) {
+          const int rl = cy + bb;
+          if (rl < 0 || rl >= nr) continue;
+          for (int aa = 0; aa < 4; ++aa)
+            cell[static_cast<size_t>(rl) * g.W + cx + aa] += std::fabs(e.w) * wx[aa] * wy[bb];
+        }
+      }
+      for (double c : cell) best[w] = std::max(best[w], c);
+    }
+  };
+  std::vector<std::thread> ts;
+  for (unsigned w = 1; w < nth; ++w) ts.emplace_back(work, w);
+  work(0);
+  for (auto& t : ts) t.join();
+  return *std::max_element(best.begin(), best.end());
+}
+
 }  // namespace
 
 hrt_status build_point_tables(const Geometry& g, PointTables& t, std::string& err) {
@@ -493,7 +561,7 @@ hrt_status build_point_tables(const Geometry& g, PointTables& t, std::string& er
     const double qh = (d.q0 + l * d.dq) * g.X / g.T;
     qx[l] = (g.alpha - std::atan(qh * qh)) / g.dtheta + g.ctheta;
   }
-  return build_lists(
+  s = build_lists(
       g, static_cast<int64_t>(d.nq) * d.ntau,
       [&](int64_t p, double& xg, double& yg, double& w) {
         const int l = static_cast<int>(p / d.ntau), i = static_cast<int>(p % d.ntau);
@@ -503,6 +571,10 @@ hrt_status build_point_tables(const Geometry& g, PointTables& t, std::string& er
         return true;
       },
       t.radon_spread, t.radon_own, err);
+  if (s != HRT_OK) return s;
+  t.cmax_data = list_cmax(g, t.data_spread);
+  t.cmax_radon = list_cmax(g, t.radon_spread);
+  return HRT_OK;
 }
 
 void alg_bytes_kernels(const Geometry& g, bool adjoint, double out[3]) {

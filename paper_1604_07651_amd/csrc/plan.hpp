@@ -19,6 +19,11 @@ constexpr int kFftRadices[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
 constexpr int kMaxBandRows = 4;
 // Static LDS of the band kernels (twiddles, reduction slots), rounded up.
 constexpr int kBandStaticLds = 4096;
+// Threads of the band kernels and of the column kernel.
+constexpr int kBandThreads = 512;
+constexpr int kColThreads = 256;
+// The in-place FFT holds at most this many complex values per thread.
+constexpr int kInplaceValues = 16;
 // Fraction bits of the log-radius coordinate in a point entry (the integer
 // part, the row relative to the band's first tap row, needs 3 bits).
 constexpr int kYFracBits = 28;
@@ -29,6 +34,12 @@ constexpr int kYFracBits = 28;
 // strided passes, measured slower: the larger footprint costs occupancy.)
 constexpr int lpad(int e) { return e; }
 constexpr int padded_len(int n) { return n; }
+
+// True when the in-place FFT can hold all butterflies of `batch` sequences
+// of f.n points with `threads` threads: ceil(batch*n/R / threads) <=
+// kInplaceValues/R for every radix R of f.
+struct FftFactors;
+bool fft_fits_inplace(const FftFactors& f, int batch, int threads);
 
 // Mixed-radix factorisation of an FFT length (radices of kFftRadices).
 struct FftFactors {
@@ -58,12 +69,17 @@ struct Geometry {
   int u0 = 0, u1 = 0;         // lattice rows touched by any point [u0, u1)
   int R = 0, nbands = 0;      // row band height (even) and band count
   int grp1 = 0, grp3 = 0;     // FFT scratch (sequences) of the band kernels
+  // FFTs in place (no LDS scratch; grp1 / grp3 sequences at a time): row FFT
+  // of the spread, row inverse FFT of the gather, column pass
+  bool inplace1 = false, inplace3 = false, inplace_col = false;
   int xw0 = 0, W = 0;         // angle columns [xw0, xw0 + W) points can touch
   int x_frac_bits = 0;         // fraction bits of the angle coordinate in a point entry
   // dynamic LDS of the band kernels: byte offset of the FFT scratch (the
-  // spread's fixed-point accumulator shares it) and the total
-  int k1_scratch = 0, k1_bytes = 0;
+  // spread's fixed-point accumulator shares it; -1 when the FFT runs in
+  // place) and the total
+  int k1_acc = 0, k1_scratch = 0, k1_bytes = 0;
   int k3_scratch = 0, k3_bytes = 0;
+  int col_bytes = 0;
   int64_t n_kept = 0;
   std::vector<int32_t> jmin;  // [nx] first kept time sample of each trace
   // Radon side, per slowness l
@@ -99,6 +115,9 @@ struct BandLists {
 
 struct PointTables {
   BandLists data_spread, data_own, radon_spread, radon_own;
+  // largest sum of |weight| x tap over the cells of a band, per point set:
+  // bounds every accumulated cell by this times the largest |input|
+  double cmax_data = 0, cmax_radon = 0;
 };
 
 // Places every kept data sample and every Radon sample on the lattice in

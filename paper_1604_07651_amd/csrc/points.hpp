@@ -1,61 +1,31 @@
-// Point work of the band kernels: the fixed-point tap accumulator of the
-// spread and the 4x4 interpolation of the gather.
+// Point work of the band kernels: the fixed-point taps of the spread and the
+// 4x4 interpolation of the gather.
 #pragma once
 
 #include "device_common.hpp"
 
 namespace hrt {
 
-// Per-thread accumulator of the 4x4 B-spline taps of consecutive points that
-// fall on the same lattice cell (a thread runs through consecutive entries
-// of its band list, which are consecutive samples of one trace or slowness
-// column, and where the lattice is coarse many of them share a cell): their
-// taps are summed in registers and reach LDS as one set of 16 atomic adds.
-//
-// The band accumulates in 64-bit fixed point: a tap value v enters as
-// round(v * scale), scale = 2^40 / (bound on |v|), added with the integer
-// LDS atomic (float LDS atomics are far slower on gfx950).  Integer sums are
-// exact and order-independent, so the band is deterministic; the quantum is
-// 2^-40 of the largest possible tap.  Band row r, window column c is
-// acc64[r * W + c]; rows outside [0, nr) are other bands' and dropped.
-struct TapAcc {
-  int cx = -1, cy = 0;  // pending cell (first tap column and row), cx < 0: none
-  float a[4][4];
-
-  __device__ __forceinline__ void flush(unsigned long long* acc64, int W, int nr,
-                                        double scale) {
-    if (cx < 0) return;
+// Adds v * B3(x - x_m) B3(y - y_n) over the taps of entry t to the band's
+// accumulator, in 32-bit fixed point: a tap value enters as round(tap *
+// scale) through the integer LDS atomic (float LDS atomics are far slower on
+// gfx950).  `v` arrives already multiplied by the scale, chosen so that
+// |every cell| <= 2^30 (the plan bounds the cells per unit input); integer
+// sums are exact and independent of order, so the band is deterministic.
+// Band row r, window column c is acc[r * W + c]; rows outside [0, nr) belong
+// to other bands and are dropped.
+__device__ __forceinline__ void spread_taps(int* acc, int W, int nr, const EntryTaps& t,
+                                            float v) {
 #pragma unroll
-    for (int bb = 0; bb < 4; ++bb) {
-      const int rl = cy + bb;
-      if (rl < 0 || rl >= nr) continue;
-      unsigned long long* row = acc64 + rl * W + cx;
+  for (int bb = 0; bb < 4; ++bb) {
+    const int rl = t.cy + bb;
+    if (rl < 0 || rl >= nr) continue;
+    int* row = acc + rl * W + t.cx;
+    const float wr = v * t.wy[bb];
 #pragma unroll
-      for (int aa = 0; aa < 4; ++aa) atomicAdd(row + aa, to_fixed(a[bb][aa], scale));
-    }
-    cx = -1;
+    for (int aa = 0; aa < 4; ++aa) atomicAdd(row + aa, __float2int_rn(wr * t.wx[aa]));
   }
-
-  // add v * B3(x - x_m) B3(y - y_n) over the taps of entry t
-  __device__ __forceinline__ void add(unsigned long long* acc64, int W, int nr, double scale,
-                                      const EntryTaps& t, float v) {
-    if (t.cx != cx || t.cy != cy) {
-      flush(acc64, W, nr, scale);
-      cx = t.cx;
-      cy = t.cy;
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-        for (int aa = 0; aa < 4; ++aa) a[bb][aa] = 0.0f;
-    }
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb) {
-      const float wr = v * t.wy[bb];
-#pragma unroll
-      for (int aa = 0; aa < 4; ++aa) a[bb][aa] += wr * t.wx[aa];
-    }
-  }
-};
+}
 
 // Sum of C[m, n] B3(x - m) B3(y - n) over the 4x4 taps of a point, C being
 // lattice rows held in LDS as complex pairs in the FFT's padded layout (held
