@@ -29,8 +29,8 @@ METRIC = ("gathers/s fwd+adj at 2048x1024 FP32 vs GPU direct sum; "
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c3_traffic.json")
 CALIB_BYTES = 256 * 1024 * 1024       # the plain device copy of --calib-copy
-STAGE_KERNELS = ["k_spread_rowfft<0>", "k_colfft<false>", "k_rowifft_gather<0>",
-                 "k_spread_rowfft<1>", "k_colfft<true>", "k_rowifft_gather<1>"]
+STAGE_KERNELS = ["k_spread<0>", "k_rowfft<0>", "k_colfft<false>", "k_rowifft", "k_gather<0>",
+                 "k_spread<1>", "k_rowfft<1>", "k_colfft<true>", "k_rowifft", "k_gather<1>"]
 
 
 def log(msg):
@@ -38,16 +38,20 @@ def log(msg):
 
 
 def kernel_alg_bytes(info, desc):
-    """Algorithmic HBM bytes per launch of each kernel (inputs read once,
-    outputs written once), same order as Plan.STAGES."""
+    """Algorithmic HBM bytes per launch of each kernel, same order as
+    Plan.STAGES: the method's own traffic (input read once, the pruned half
+    spectrum written by the row FFT, read and written by the column pass with
+    K, read by the row inverse FFT, output written once).  The partial rows
+    between spread and row FFT and the real rows between inverse FFT and
+    gather are not algorithmic: they show up in the measured traffic."""
     U = info["row_hi"] - info["row_lo"]
     spec = 8.0 * info["k1_kept"] * U
     kmul = 8.0 * info["k1_kept"] * info["k2_kept"]
     data_in = 4.0 * info["n_kept"]
     data_out = 4.0 * desc.nx * desc.nt
     radon = 4.0 * desc.nq * desc.ntau
-    return [data_in + spec, 2 * spec + kmul, spec + radon,
-            radon + spec, 2 * spec + kmul, spec + data_out]
+    return [data_in, spec, 2 * spec + kmul, spec, radon,
+            radon, spec, 2 * spec + kmul, spec, data_out]
 
 
 def kernel_source_hash():
@@ -209,7 +213,7 @@ def main():
 
     # per-kernel HIP events on the launch stream, over the same number of steps
     log("per-kernel event timing")
-    plan.profile_begin(6 * args.steps)
+    plan.profile_begin(len(plan.STAGES) * args.steps)
     for _ in range(args.steps):
         step()
     prof = plan.profile_end()

@@ -19,13 +19,12 @@ constexpr int kAbsMaxBlocks = 256;  // partial maxima of the input
 struct DevGeo {
   int nt, nx;
   int Mt, Mr, K1, K2, u0, u1, R, nbands;
-  int grp1, grp3;     // FFT scratch sequences of the band kernels
   int xw0, W;         // angle columns [xw0, xw0 + W) that points can touch
   int x_frac_bits;    // fraction bits of the angle coordinate of a point entry
-  // byte offsets in the dynamic LDS: the spread's fixed-point rows, the FFT
-  // scratch of the spread and of the gather (-1: the FFT runs in place)
-  int k1_acc, k1_scratch, k3_scratch;
-  int col_inplace;              // the column FFT runs in place
+  // row FFTs: sequences per group, byte offset of the LDS scratch (-1: in
+  // place); the column FFT in place or not
+  int row_group, row_scratch;
+  int col_inplace;
   float knorm;                  // 1/(Mt Mr): both inverse FFTs are unnormalised
   float cmax_data, cmax_radon;  // bounds of the accumulated cells per unit input
   const int* jmin;              // first kept time sample of each trace

@@ -53,11 +53,15 @@ struct hrt_plan_s {
   float2* tw_t = nullptr;
   float2* tw_r = nullptr;
   int* jmin = nullptr;
-  uint4* ent[4] = {};      // band lists (kDataSpread ... kRadonOwn)
-  int64_t* off[4] = {};
-  int* order[4] = {};      // launch order of the bands per list, longest first
+  // point lists (kDataSpread ... kRadonOwn), cut into chunks
+  uint4* ent[4] = {};
+  int64_t* chunk_off[4] = {};
+  int* chunk_band[4] = {};
+  int* band_chunk[4] = {};
+  int nchunks[4] = {};
+  int* Hp = nullptr;        // partial fixed-point rows of the spread chunks
+  float* Cr = nullptr;      // real lattice rows after the inverse row FFT
   float* absmax = nullptr;  // kAbsMaxBlocks partial maxima of the current input
-  size_t lds_k1 = 0, lds_k2 = 0, lds_k3 = 0;
   // per-kernel timing (hrt_profile_begin / hrt_profile_end)
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_stage;
@@ -126,11 +130,14 @@ hrt_status upload(T* dst, const std::vector<T>& src) {
 }
 
 void free_plan(hrt_plan_s* p) {
-  void* ptrs[] = {p->S,      p->K,      p->tw_t,   p->tw_r,   p->jmin,  p->absmax,
-                  p->ent[0], p->ent[1], p->ent[2], p->ent[3], p->off[0], p->off[1],
-                  p->off[2], p->off[3], p->order[0], p->order[1], p->order[2], p->order[3]};
+  void* ptrs[] = {p->S, p->K, p->tw_t, p->tw_r, p->jmin, p->absmax, p->Hp, p->Cr};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  for (int i = 0; i < 4; ++i) {
+    void* lists[] = {p->ent[i], p->chunk_off[i], p->chunk_band[i], p->band_chunk[i]};
+    for (void* q : lists)
+      if (q) (void)hipFree(q);
+  }
 }
 
 double b_squared(double xi) {  // (sinc^4)^2 of the cubic B-spline
@@ -268,10 +275,7 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
     return set_err(s, err);
   }
   const Geometry& g = p->g;
-  p->lds_k1 = static_cast<size_t>(g.k1_bytes);
-  p->lds_k2 = static_cast<size_t>(g.col_bytes);
-  p->lds_k3 = static_cast<size_t>(g.k3_bytes);
-  if (static_cast<int64_t>(p->lds_k2) > std::min<int64_t>(lds_max, 163840) - 4096) {
+  if (static_cast<int64_t>(g.col_bytes) > std::min<int64_t>(lds_max, 163840) - 4096) {
     delete p;
     return set_err(HRT_ERR_UNSUPPORTED, "log-radius axis too long for an LDS column");
   }
@@ -306,16 +310,14 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
                                  &tab.radon_own};
     for (int i = 0; i < 4; ++i) {
       const BandLists& L = *lists[i];
-      // longest lists first, so that the bands that start late are short
-      std::vector<int> ord(g.nbands);
-      for (int b = 0; b < g.nbands; ++b) ord[b] = b;
-      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
-        return L.off[x + 1] - L.off[x] > L.off[y + 1] - L.off[y];
-      });
+      p->nchunks[i] = static_cast<int>(L.chunk_band.size());
       if ((s = dev_alloc(&p->ent[i], std::max<size_t>(1, L.e.size()), total)) ||
-          (s = dev_alloc(&p->off[i], L.off.size(), total)) ||
-          (s = dev_alloc(&p->order[i], ord.size(), total)) ||
-          (s = upload(p->off[i], L.off)) || (s = upload(p->order[i], ord))) {
+          (s = dev_alloc(&p->chunk_off[i], L.chunk_off.size(), total)) ||
+          (s = dev_alloc(&p->chunk_band[i], L.chunk_band.size(), total)) ||
+          (s = dev_alloc(&p->band_chunk[i], L.band_chunk.size(), total)) ||
+          (s = upload(p->chunk_off[i], L.chunk_off)) ||
+          (s = upload(p->chunk_band[i], L.chunk_band)) ||
+          (s = upload(p->band_chunk[i], L.band_chunk))) {
         free_plan(p);
         delete p;
         return s;
@@ -329,6 +331,15 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
           return hip_err(e, "upload point lists");
         }
       }
+    }
+    // one partial per spread chunk, and the real rows after the inverse FFT
+    const size_t parts = static_cast<size_t>(
+        std::max(p->nchunks[kDataSpread], p->nchunks[kRadonSpread]));
+    if ((s = dev_alloc(&p->Hp, parts * g.R * g.W, total)) ||
+        (s = dev_alloc(&p->Cr, static_cast<size_t>(g.u1 - g.u0) * g.W, total))) {
+      free_plan(p);
+      delete p;
+      return s;
     }
   }
   hipError_t e = hipMemset(p->S, 0, static_cast<size_t>(g.K1) * g.Mr * sizeof(float2));
@@ -348,18 +359,24 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
     // (the device limit less its static LDS), whatever this plan needs
     std::lock_guard<std::mutex> lk(g_attr_mu);
     const int64_t cap = std::min<int64_t>(lds_max, 163840);
-    const void* fns[] = {reinterpret_cast<const void*>(&k_spread_rowfft<0>),
-                         reinterpret_cast<const void*>(&k_spread_rowfft<1>),
+    const void* fns[] = {reinterpret_cast<const void*>(&k_spread<0>),
+                         reinterpret_cast<const void*>(&k_spread<1>),
+                         reinterpret_cast<const void*>(&k_rowfft<0>),
+                         reinterpret_cast<const void*>(&k_rowfft<1>),
                          reinterpret_cast<const void*>(&k_colfft<false>),
                          reinterpret_cast<const void*>(&k_colfft<true>),
-                         reinterpret_cast<const void*>(&k_rowifft_gather<0>),
-                         reinterpret_cast<const void*>(&k_rowifft_gather<1>)};
-    const size_t need[] = {p->lds_k1, p->lds_k1, p->lds_k2, p->lds_k2, p->lds_k3, p->lds_k3};
+                         reinterpret_cast<const void*>(&k_rowifft),
+                         reinterpret_cast<const void*>(&k_gather<0>),
+                         reinterpret_cast<const void*>(&k_gather<1>)};
+    const int need[] = {g.spread_bytes, g.spread_bytes, g.row_bytes, g.row_bytes,
+                        g.col_bytes,    g.col_bytes,    g.row_bytes, g.gather_bytes,
+                        g.gather_bytes};
+    constexpr int nfn = sizeof(fns) / sizeof(fns[0]);
     struct {
       const void* fn;
       size_t bytes;
-    } attrs[6];
-    for (int i = 0; i < 6; ++i) {
+    } attrs[nfn];
+    for (int i = 0; i < nfn; ++i) {
       hipFuncAttributes fa;
       hipError_t r = hipFuncGetAttributes(&fa, fns[i]);
       if (r != hipSuccess) {
@@ -390,9 +407,9 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
   DevGeo& G = p->dg;
   G.nt = g.d.nt; G.nx = g.d.nx;
   G.Mt = g.Mt; G.Mr = g.Mr; G.K1 = g.K1; G.K2 = g.K2; G.u0 = g.u0; G.u1 = g.u1;
-  G.R = g.R; G.nbands = g.nbands; G.grp1 = g.grp1; G.grp3 = g.grp3;
+  G.R = g.R; G.nbands = g.nbands;
   G.xw0 = g.xw0; G.W = g.W; G.x_frac_bits = g.x_frac_bits;
-  G.k1_acc = g.k1_acc; G.k1_scratch = g.k1_scratch; G.k3_scratch = g.k3_scratch;
+  G.row_group = g.row_group; G.row_scratch = g.row_scratch;
   G.col_inplace = g.inplace_col ? 1 : 0;
   G.knorm = static_cast<float>(1.0 / (static_cast<double>(g.Mt) * g.Mr));
   G.cmax_data = cmax_data;
@@ -456,41 +473,48 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const Geometry& g = p->g;
   const dim3 bands(g.nbands);
-  if (!adjoint) {
-    {
-      StageTimer t(p, st, 0);
-      k_absmax<<<kAbsMaxBlocks, 256, 0, st>>>(in, static_cast<int64_t>(n_in), p->absmax);
-      k_spread_rowfft<0><<<bands, kNtBand, p->lds_k1, st>>>(
-          p->dg, p->ft, p->tw_t, in, p->absmax, p->ent[kDataSpread], p->off[kDataSpread],
-          p->order[kDataSpread], p->S);
-    }
-    {
-      StageTimer t(p, st, 1);
-      k_colfft<false><<<g.K1, kNtCol, p->lds_k2, st>>>(p->dg, p->fr, p->tw_r, p->S, p->K);
-    }
-    {
-      StageTimer t(p, st, 2);
-      k_rowifft_gather<0><<<bands, kNtBand, p->lds_k3, st>>>(
-          p->dg, p->ft, p->tw_t, p->S, p->ent[kRadonOwn], p->off[kRadonOwn], p->order[kRadonOwn],
-          out);
-    }
-  } else {
-    {
-      StageTimer t(p, st, 3);
-      k_absmax<<<kAbsMaxBlocks, 256, 0, st>>>(in, static_cast<int64_t>(n_in), p->absmax);
-      k_spread_rowfft<1><<<bands, kNtBand, p->lds_k1, st>>>(
-          p->dg, p->ft, p->tw_t, in, p->absmax, p->ent[kRadonSpread], p->off[kRadonSpread],
-          p->order[kRadonSpread], p->S);
-    }
-    {
-      StageTimer t(p, st, 4);
-      k_colfft<true><<<g.K1, kNtCol, p->lds_k2, st>>>(p->dg, p->fr, p->tw_r, p->S, p->K);
-    }
-    {
-      StageTimer t(p, st, 5);
-      k_rowifft_gather<1><<<bands, kNtBand, p->lds_k3, st>>>(
-          p->dg, p->ft, p->tw_t, p->S, p->ent[kDataOwn], p->off[kDataOwn], p->order[kDataOwn], out);
-    }
+  const size_t sb = g.spread_bytes, rb = g.row_bytes, cb = g.col_bytes, gb = g.gather_bytes;
+  const int sl = adjoint ? kRadonSpread : kDataSpread;  // list spread
+  const int gl = adjoint ? kDataOwn : kRadonOwn;        // list gathered at
+  const int t0 = adjoint ? 5 : 0;                       // profile slots
+  {
+    StageTimer t(p, st, t0);
+    k_absmax<<<kAbsMaxBlocks, 256, 0, st>>>(in, static_cast<int64_t>(n_in), p->absmax);
+    if (adjoint)
+      k_spread<1><<<p->nchunks[sl], kNtBand, sb, st>>>(p->dg, in, p->absmax, p->ent[sl],
+                                                       p->chunk_off[sl], p->chunk_band[sl], p->Hp);
+    else
+      k_spread<0><<<p->nchunks[sl], kNtBand, sb, st>>>(p->dg, in, p->absmax, p->ent[sl],
+                                                       p->chunk_off[sl], p->chunk_band[sl], p->Hp);
+  }
+  {
+    StageTimer t(p, st, t0 + 1);
+    if (adjoint)
+      k_rowfft<1><<<bands, kNtBand, rb, st>>>(p->dg, p->ft, p->tw_t, p->absmax, p->Hp,
+                                              p->band_chunk[sl], p->S);
+    else
+      k_rowfft<0><<<bands, kNtBand, rb, st>>>(p->dg, p->ft, p->tw_t, p->absmax, p->Hp,
+                                              p->band_chunk[sl], p->S);
+  }
+  {
+    StageTimer t(p, st, t0 + 2);
+    if (adjoint)
+      k_colfft<true><<<g.K1, kNtCol, cb, st>>>(p->dg, p->fr, p->tw_r, p->S, p->K);
+    else
+      k_colfft<false><<<g.K1, kNtCol, cb, st>>>(p->dg, p->fr, p->tw_r, p->S, p->K);
+  }
+  {
+    StageTimer t(p, st, t0 + 3);
+    k_rowifft<<<bands, kNtBand, rb, st>>>(p->dg, p->ft, p->tw_t, p->S, p->Cr);
+  }
+  {
+    StageTimer t(p, st, t0 + 4);
+    if (adjoint)
+      k_gather<1><<<p->nchunks[gl], kNtBand, gb, st>>>(p->dg, p->Cr, p->ent[gl], p->chunk_off[gl],
+                                                       p->chunk_band[gl], p->nchunks[gl], out);
+    else
+      k_gather<0><<<p->nchunks[gl], kNtBand, gb, st>>>(p->dg, p->Cr, p->ent[gl], p->chunk_off[gl],
+                                                       p->chunk_band[gl], p->nchunks[gl], out);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, adjoint ? "adjoint launch" : "forward launch");
@@ -584,8 +608,8 @@ hrt_status hrt_profile_end(hrt_plan_t p, double* ms_sum, int64_t* count) {
   hrt_status s = check_plan(p);
   if (s != HRT_OK) return s;
   DeviceGuard guard(p->device);
-  double ms[6] = {0, 0, 0, 0, 0, 0};
-  int64_t cnt[6] = {0, 0, 0, 0, 0, 0};
+  double ms[HRT_PROFILE_SLOTS] = {};
+  int64_t cnt[HRT_PROFILE_SLOTS] = {};
   hrt_status out = HRT_OK;
   for (int i = 0; i < p->prof_used; ++i) {
     float t = 0.f;
@@ -599,7 +623,7 @@ hrt_status hrt_profile_end(hrt_plan_t p, double* ms_sum, int64_t* count) {
     cnt[p->prof_stage[i]] += 1;
   }
   release_profile(p);
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < HRT_PROFILE_SLOTS; ++i) {
     if (ms_sum) ms_sum[i] = ms[i];
     if (count) count[i] = cnt[i];
   }

@@ -1,23 +1,28 @@
 // The kernels of one direction of the log-polar transform (Section 2.2,
-// eqs. B3tx2, lok, B3tauq; Section 3 for the adjoint):
+// eqs. B3tx2, lok, B3tauq; Section 3 for the adjoint).  The lattice rows
+// [u0, u1) are cut into bands of R rows; the point lists of the plan are cut
+// into chunks of at most a fixed number of entries, so that the point
+// kernels get equal work whatever the density of points along the lattice.
 //
-//   k_absmax          largest |input| (fixes the spread's fixed-point scale)
-//   k_spread_rowfft   one workgroup per band of R lattice rows: smear every
-//                     sample whose B-spline stencil reaches the band (data
-//                     samples for the forward, Radon samples for the
-//                     adjoint; the band's list of placed points comes from
-//                     the plan), then the FFT along the angle, two real
-//                     rows per complex sequence; store k1 < K1 of the half
-//                     spectrum, column-major S[k1][row].
-//   k_colfft          one workgroup per kept k1: FFT along the log radius,
-//                     multiply by the kernel multiplier (its conjugate for
-//                     the adjoint), inverse FFT.
-//   k_rowifft_gather  one workgroup per band: Hermitian completion and
-//                     inverse FFT along the angle of the band plus a 3-row
-//                     halo, then the 4x4 B-spline interpolation at every
-//                     sample whose base row lies in the band (Radon samples
-//                     for the forward, data samples times their smear weight
-//                     for the adjoint).
+//   k_absmax   largest |input| (fixes the spread's fixed-point scale)
+//   k_spread   one workgroup per chunk of a band's spread list: smear the
+//              chunk's samples (data samples for the forward, Radon samples
+//              for the adjoint) onto the band's rows in LDS, store the rows
+//              (32-bit fixed point) as the chunk's partial Hp[chunk]
+//   k_rowfft   one workgroup per band: sum the band's partials, FFT along
+//              the angle, two real rows per complex sequence; store k1 < K1
+//              of the half spectrum, column-major S[k1][row]
+//   k_colfft   one workgroup per kept k1: FFT along the log radius, multiply
+//              by the kernel multiplier (its conjugate for the adjoint),
+//              inverse FFT
+//   k_rowifft  one workgroup per band: Hermitian completion and inverse FFT
+//              along the angle; store the real rows, window columns only,
+//              as Cr[row - u0][column - xw0]
+//   k_gather   one workgroup per chunk of a band's owned list: stage the
+//              band's rows plus a 3-row halo from Cr in LDS and interpolate
+//              at each sample (Radon samples times X cos(psi)/a for the
+//              forward, data samples times their smear weight for the
+//              adjoint, which also zeroes the samples outside the trapezoid)
 #pragma once
 
 #include "points.hpp"
@@ -48,51 +53,48 @@ __global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ x, int
     partial[blockIdx.x] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
 }
 
-// Spread of one point set (MODE 0: data samples of f[nx][nt], forward;
-// MODE 1: Radon samples of g[nq][ntau], adjoint) from the band's list
-// ent[off[band] .. off[band+1]); workgroup i takes band order[i] (heaviest
-// lists first).  Dynamic LDS: the band's complex pairs at 0 (they first
-// stage the point list), the 32-bit fixed-point rows at k1_acc, the FFT
-// scratch (if any) at k1_scratch over the fixed-point rows.
-template <int MODE>
-__global__ __launch_bounds__(kNtBand, 4) void k_spread_rowfft(
-    DevGeo G, FftDev F, const float2* __restrict__ tw, const float* __restrict__ in,
-    const float* __restrict__ absmax, const uint4* __restrict__ ent,
-    const int64_t* __restrict__ off, const int* __restrict__ order, float2* __restrict__ S) {
-  extern __shared__ float2 lds[];
-  __shared__ float s_wave[kNtBand / 64];
-  __shared__ float2 s_tw[kTwLds];
-  const int band = order[blockIdx.x];
-  load_twiddles<kNtBand>(s_tw, tw, G.Mt);
-  char* base = reinterpret_cast<char*>(lds);
-  int* acc = reinterpret_cast<int*>(base + G.k1_acc);
-  const int n0 = G.u0 + band * G.R;
-  const int nr = min(G.R, G.u1 - n0);
-  const int npair = nr >> 1;
-  const int Mt = G.Mt, W = G.W, SP = padded_len(G.Mt);
-
-  // largest |input| (from k_absmax) fixes the fixed-point scale: every
-  // cell stays within 2^30 (cmax bounds a cell per unit input)
+// The spread's fixed-point scale: every accumulated cell stays within 2^30
+// (cmax bounds a cell per unit of input); 0 for an all-zero or non-finite
+// input (the latter is reported through `finite`).
+__device__ __forceinline__ float spread_scale(const float* __restrict__ absmax, float cmax,
+                                              float* s_wave, bool& finite) {
   float vmax = 0.0f;
   for (int i = threadIdx.x; i < kAbsMaxBlocks; i += kNtBand) vmax = fmaxf(vmax, absmax[i]);
   vmax = block_max(vmax, s_wave);
-  const float cmax = MODE == 0 ? G.cmax_data : G.cmax_radon;
-  const bool finite = vmax <= 3.0e38f;  // false for inf and NaN
-  const float scale = (vmax > 0.0f && finite) ? 1073741824.0f / (cmax * vmax) : 0.0f;
+  finite = vmax <= 3.0e38f;  // false for inf and NaN
+  return (vmax > 0.0f && finite) ? 1073741824.0f / (cmax * vmax) : 0.0f;
+}
+
+// Spread of one chunk (MODE 0: data samples of f[nx][nt]; MODE 1: Radon
+// samples of g[nq][ntau]).  Dynamic LDS: the band's R x W fixed-point rows,
+// then a staging buffer for kSpreadStage entries.  The chunk's entries are
+// read coalesced into the staging buffer; thread s then takes a contiguous
+// segment of it, segments dealt lane-major so that the lanes of a wave work
+// far apart on the lattice.
+template <int MODE>
+__global__ __launch_bounds__(kNtBand) void k_spread(
+    DevGeo G, const float* __restrict__ in, const float* __restrict__ absmax,
+    const uint4* __restrict__ ent, const int64_t* __restrict__ chunk_off,
+    const int* __restrict__ chunk_band, int* __restrict__ Hp) {
+  extern __shared__ int lds_i[];
+  __shared__ float s_wave[kNtBand / 64];
+  const int chunk = blockIdx.x;
+  const int band = chunk_band[chunk];
+  const int n0 = G.u0 + band * G.R;
+  const int nr = min(G.R, G.u1 - n0);
+  const int W = G.W;
+  int* acc = lds_i;
+  uint4* stage = reinterpret_cast<uint4*>(lds_i + G.R * W);
+  bool finite;
+  const float scale = spread_scale(absmax, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave,
+                                   finite);
   for (int i = threadIdx.x; i < nr * W; i += kNtBand) acc[i] = 0;
   __syncthreads();
-
-  // smear the band's points (skipped when all inputs are 0).  The list is
-  // read in chunks, coalesced, into the pair rows (idle until the FFT); in a
-  // chunk thread s takes a contiguous segment, segments dealt lane-major so
-  // that the lanes of a wave work far apart on the lattice.
   if (scale > 0.0f) {
-    uint4* stage = reinterpret_cast<uint4*>(base);
-    const int cap = G.k1_acc / static_cast<int>(sizeof(uint4));
-    const int64_t e0 = off[band], e1 = off[band + 1];
+    const int64_t e0 = chunk_off[chunk], e1 = chunk_off[chunk + 1];
     const int seg = (threadIdx.x & 63) * (kNtBand / 64) + (threadIdx.x >> 6);
-    for (int64_t c0 = e0; c0 < e1; c0 += cap) {
-      const int n = static_cast<int>(min(static_cast<int64_t>(cap), e1 - c0));
+    for (int64_t c0 = e0; c0 < e1; c0 += kSpreadStage) {
+      const int n = static_cast<int>(min(static_cast<int64_t>(kSpreadStage), e1 - c0));
       for (int i = threadIdx.x; i < n; i += kNtBand) stage[i] = ent[c0 + i];
       __syncthreads();
       const int per = (n + kNtBand - 1) / kNtBand;
@@ -116,25 +118,55 @@ __global__ __launch_bounds__(kNtBand, 4) void k_spread_rowfft(
       __syncthreads();
     }
   }
-  __syncthreads();
+  // the chunk's partial rows, R x W (rows past nr unused)
+  int* dst = Hp + static_cast<size_t>(chunk) * G.R * W;
+  for (int i = threadIdx.x; i < nr * W; i += kNtBand) dst[i] = acc[i];
+}
 
-  // fixed point -> float, rows (2p, 2p+1) into complex pair p (zero outside
-  // the columns points can reach)
+// Row FFT of one band: the sum of its chunks' partials, fixed point to
+// float (NaN everywhere for a non-finite input), rows (2p, 2p+1) into
+// complex pair p, FFT along the angle, and the k1 < K1 half spectrum of both
+// rows to S.  Dynamic LDS: the pairs, then the FFT scratch (if any).
+template <int MODE>
+__global__ __launch_bounds__(kNtBand) void k_rowfft(
+    DevGeo G, FftDev F, const float2* __restrict__ tw, const float* __restrict__ absmax,
+    const int* __restrict__ Hp, const int* __restrict__ band_chunk, float2* __restrict__ S) {
+  extern __shared__ float2 lds[];
+  __shared__ float s_wave[kNtBand / 64];
+  __shared__ float2 s_tw[kTwLds];
+  const int band = blockIdx.x;
+  load_twiddles<kNtBand>(s_tw, tw, G.Mt);
+  const int n0 = G.u0 + band * G.R;
+  const int nr = min(G.R, G.u1 - n0);
+  const int npair = nr >> 1;
+  const int Mt = G.Mt, W = G.W, SP = padded_len(G.Mt);
+  bool finite;
+  const float scale = spread_scale(absmax, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave,
+                                   finite);
   const float inv = scale > 0.0f ? 1.0f / scale : 0.0f;
   const float bad = finite ? 0.0f : __int_as_float(0x7fc00000);
+  const int q0 = band_chunk[band], q1 = band_chunk[band + 1];
   for (int idx = threadIdx.x; idx < npair * Mt; idx += kNtBand) {
     const int p = idx / Mt;
     const int m = idx - p * Mt;
     const int c = m - G.xw0;
     float lo = 0.0f, hi = 0.0f;
     if (c >= 0 && c < W) {
-      lo = static_cast<float>(acc[(2 * p) * W + c]) * inv;
-      hi = static_cast<float>(acc[(2 * p + 1) * W + c]) * inv;
+      // exact integer sums (two's complement, so order does not matter)
+      int a = 0, b = 0;
+      for (int q = q0; q < q1; ++q) {
+        const int* part = Hp + static_cast<size_t>(q) * G.R * W;
+        a += part[(2 * p) * W + c];
+        b += part[(2 * p + 1) * W + c];
+      }
+      lo = static_cast<float>(a) * inv;
+      hi = static_cast<float>(b) * inv;
     }
     lds[p * SP + lpad(m)] = make_float2(lo + bad, hi + bad);
   }
   __syncthreads();
-  fft_rows<kNtBand, false>(lds, SP, npair, fft_scratch(base, G.k1_scratch), G.grp1, F, s_tw);
+  fft_rows<kNtBand, false>(lds, SP, npair, fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
+                           G.row_group, F, s_tw);
   // two real rows per complex sequence: X1 = (Z[k] + conj Z[-k])/2,
   // X2 = (Z[k] - conj Z[-k])/(2i); keep k1 < K1
   for (int idx = threadIdx.x; idx < G.K1 * npair; idx += kNtBand) {
@@ -182,56 +214,85 @@ __global__ __launch_bounds__(kNtCol) void k_colfft(DevGeo G, FftDev F,
   for (int n = G.u0 + threadIdx.x; n < G.u1; n += kNtCol) col[n] = lds[lpad(n)];
 }
 
-// Gather at the points the band owns (MODE 0: Radon samples into
-// g[nq][ntau], forward; MODE 1: data samples times their smear weight into
-// f[nx][nt], adjoint, zero outside the trapezoid), from the band's list
-// ent[off[band] .. off[band+1]), workgroup i taking band order[i].  Dynamic
-// LDS: the band's rows plus halo as
-// complex pairs at 0, the FFT scratch (if any) at k3_scratch.
-template <int MODE>
-__global__ __launch_bounds__(kNtBand, 4) void k_rowifft_gather(
-    DevGeo G, FftDev F, const float2* __restrict__ tw, const float2* __restrict__ S,
-    const uint4* __restrict__ ent, const int64_t* __restrict__ off, const int* __restrict__ order,
-    float* __restrict__ out) {
+// Inverse row FFT of one band: Z = X1 + i X2 for rows (2p, 2p+1) with the
+// Hermitian completion Z[-k], inverse FFT along the angle, real rows to Cr
+// (window columns only).  Dynamic LDS: the pairs, then the FFT scratch.
+__global__ __launch_bounds__(kNtBand) void k_rowifft(DevGeo G, FftDev F,
+                                                     const float2* __restrict__ tw,
+                                                     const float2* __restrict__ S,
+                                                     float* __restrict__ Cr) {
   extern __shared__ float2 lds[];
   __shared__ float2 s_tw[kTwLds];
-  const int band = order[blockIdx.x];
+  const int band = blockIdx.x;
   load_twiddles<kNtBand>(s_tw, tw, G.Mt);
-  char* base = reinterpret_cast<char*>(lds);
-  const float* ldsf = reinterpret_cast<const float*>(lds);
+  const int n0 = G.u0 + band * G.R;
+  const int nr = min(G.R, G.u1 - n0);
+  const int npair = nr >> 1;
+  const int Mt = G.Mt, SP = padded_len(G.Mt), W = G.W;
+  for (int i = threadIdx.x; i < npair * SP; i += kNtBand) lds[i] = make_float2(0.f, 0.f);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < G.K1 * npair; idx += kNtBand) {
+    const int k = idx / npair;
+    const int p = idx - k * npair;
+    const float4 x = *reinterpret_cast<const float4*>(S + static_cast<size_t>(k) * G.Mr + n0 +
+                                                      2 * p);
+    // X1 = (x.x, x.y), X2 = (x.z, x.w)
+    lds[p * SP + lpad(k)] = make_float2(x.x - x.w, x.y + x.z);
+    if (k > 0) lds[p * SP + lpad(Mt - k)] = make_float2(x.x + x.w, x.z - x.y);
+  }
+  __syncthreads();
+  fft_rows<kNtBand, true>(lds, SP, npair, fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
+                          G.row_group, F, s_tw);
+  float* dst = Cr + static_cast<size_t>(n0 - G.u0) * W;
+  for (int idx = threadIdx.x; idx < npair * W; idx += kNtBand) {
+    const int p = idx / W;
+    const int c = idx - p * W;
+    const float2 z = lds[p * SP + lpad(G.xw0 + c)];
+    dst[(2 * p) * W + c] = z.x;
+    dst[(2 * p + 1) * W + c] = z.y;
+  }
+}
+
+// Gather for one chunk of a band's owned list (MODE 0: into g[nq][ntau];
+// MODE 1: into f[nx][nt], plus zeros outside the trapezoid, traces dealt
+// over the chunks).  Dynamic LDS: rows [L0, L1) of Cr, the band's rows and
+// the halo its points' stencils reach.  One point per thread, consecutive
+// threads on consecutive entries.
+template <int MODE>
+__global__ __launch_bounds__(kNtBand) void k_gather(
+    DevGeo G, const float* __restrict__ Cr, const uint4* __restrict__ ent,
+    const int64_t* __restrict__ chunk_off, const int* __restrict__ chunk_band,
+    int nchunks, float* __restrict__ out) {
+  extern __shared__ float rows[];
+  const int chunk = blockIdx.x;
+  const int band = chunk_band[chunk];
   const int n0 = G.u0 + band * G.R;
   const int nr = min(G.R, G.u1 - n0);
   const int L0 = max(G.u0, n0 - 1);
   const int L1 = min(G.u1, n0 + nr + 2);
-  const int npair = (L1 - L0 + 1) >> 1;
-  const int Mt = G.Mt, SP = padded_len(G.Mt);
-  for (int i = threadIdx.x; i < npair * SP; i += kNtBand) lds[i] = make_float2(0.f, 0.f);
+  const int W = G.W;
+  const float4* src = reinterpret_cast<const float4*>(Cr + static_cast<size_t>(L0 - G.u0) * W);
+  float4* rows4 = reinterpret_cast<float4*>(rows);
+  for (int i = threadIdx.x; i < (L1 - L0) * W / 4; i += kNtBand) rows4[i] = src[i];
   __syncthreads();
-  // Z = X1 + i X2 for two real rows, Hermitian completion Z[-k]
-  for (int idx = threadIdx.x; idx < G.K1 * npair; idx += kNtBand) {
-    const int k = idx / npair;
-    const int p = idx - k * npair;
-    const int ra = L0 + 2 * p;
-    const float2* src = S + static_cast<size_t>(k) * G.Mr;
-    const float2 X1 = src[ra];
-    const float2 X2 = (ra + 1 < L1) ? src[ra + 1] : make_float2(0.f, 0.f);
-    lds[p * SP + lpad(k)] = make_float2(X1.x - X2.y, X1.y + X2.x);
-    if (k > 0) lds[p * SP + lpad(Mt - k)] = make_float2(X1.x + X2.y, X2.x - X1.y);
-  }
-  __syncthreads();
-  fft_rows<kNtBand, true>(lds, SP, npair, fft_scratch(base, G.k3_scratch), G.grp3, F, s_tw);
-  // one point per thread, consecutive threads on consecutive entries
-  const int64_t e0 = off[band], e1 = off[band + 1];
-  const int nheld = L1 - L0, shift = n0 - L0;
+  const int64_t e0 = chunk_off[chunk], e1 = chunk_off[chunk + 1];
+  const int shift = n0 - L0;  // held row of lattice row n0
+  const int nheld = L1 - L0;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += kNtBand) {
     const uint4 E = ent[e];
     const EntryTaps tp = decode_entry(E.y, E.z, G.x_frac_bits);
-    out[E.x] = __uint_as_float(E.w) *
-               gather_taps(ldsf, SP, nheld, tp.cy + shift, G.xw0 + tp.cx, tp.wx, tp.wy);
+    float acc = 0.0f;
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      const int rl = tp.cy + shift + bb;
+      if (rl < 0 || rl >= nheld) continue;
+      const float* r = rows + rl * W + tp.cx;
+      acc += tp.wy[bb] * (r[0] * tp.wx[0] + r[1] * tp.wx[1] + r[2] * tp.wx[2] + r[3] * tp.wx[3]);
+    }
+    out[E.x] = __uint_as_float(E.w) * acc;
   }
   if (MODE == 1) {
-    // samples outside the trapezoid: each trace zeroed by one band
-    for (int k = band; k < G.nx; k += G.nbands) {
+    for (int k = chunk; k < G.nx; k += nchunks) {
       float* fk = out + static_cast<size_t>(k) * G.nt;
       for (int j = threadIdx.x; j < G.jmin[k]; j += kNtBand) fk[j] = 0.0f;
     }

@@ -322,7 +322,12 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   {
     const double half = 0.5 * g.beta / g.dtheta;
     g.xw0 = std::max(0, static_cast<int>(std::floor(g.ctheta - half)) - 3);
-    const int xw1 = std::min(g.Mt, static_cast<int>(std::ceil(g.ctheta + half)) + 4);
+    int xw1 = std::min(g.Mt, static_cast<int>(std::ceil(g.ctheta + half)) + 4);
+    while ((xw1 - g.xw0) % 4 != 0) {  // whole float4 rows
+      if (xw1 < g.Mt) ++xw1;
+      else if (g.xw0 > 0) --g.xw0;
+      else return fail(err, HRT_ERR_UNSUPPORTED, "angle window not a multiple of 4");
+    }
     g.W = xw1 - g.xw0;
   }
   if (xq_min < g.xw0 || xq_max >= g.xw0 + g.W)
@@ -355,38 +360,26 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
       if (fft_fits_inplace(g.fft_t, b, kBandThreads)) grp = b;
     return grp;
   };
-  auto layout = [&](int R, int grp3, bool commit) {
-    // spread: R/2 complex pairs (they also stage the point list), then the
-    // 32-bit fixed-point rows, which the FFT scratch reuses when the FFT
-    // does not run in place
-    const int in1 = inplace_group(R / 2);
-    const int64_t d1 = (R / 2) * seq;
-    const int64_t acc = static_cast<int64_t>(R) * g.W * 4;
-    const int64_t b1 = d1 + std::max<int64_t>(acc, in1 ? 0 : (R / 2) * seq);
-    // gather: band + 3 halo rows as pairs, then the FFT scratch if needed
-    const int in3 = inplace_group((R + 4) / 2);
-    const int64_t d3 = ((R + 4) / 2) * seq;
-    const int64_t b3 = d3 + (in3 ? 0 : grp3 * seq);
+  auto layout = [&](int R, bool commit) {
+    const int64_t spread = static_cast<int64_t>(R) * g.W * 4 + int64_t{kSpreadStage} * 16;
+    const int grp = inplace_group(R / 2);
+    const int64_t pairs = (R / 2) * seq;
+    const int64_t row = pairs + (grp ? 0 : pairs);
+    const int64_t gather = static_cast<int64_t>(R + 3) * g.W * 4;
     if (commit) {
-      g.inplace1 = in1 > 0;
-      g.inplace3 = in3 > 0;
-      g.grp1 = in1 ? in1 : R / 2;
-      g.grp3 = in3 ? in3 : grp3;
-      g.k1_acc = static_cast<int>(d1);
-      g.k1_scratch = in1 ? -1 : static_cast<int>(d1);
-      g.k1_bytes = static_cast<int>(b1);
-      g.k3_scratch = in3 ? -1 : static_cast<int>(d3);
-      g.k3_bytes = static_cast<int>(b3);
+      g.spread_bytes = static_cast<int>(spread);
+      g.row_bytes = static_cast<int>(row);
+      g.gather_bytes = static_cast<int>(gather);
+      g.row_group = grp ? grp : R / 2;
+      g.row_scratch = grp ? -1 : static_cast<int>(pairs);
     }
-    return std::max(b1, b3);
+    return std::max(std::max(spread, row), gather);
   };
   g.R = kMaxBandRows;
-  while (g.R > 2 && layout(g.R, 1, false) > lds_bytes) g.R -= 2;
-  if (layout(g.R, 1, false) > lds_bytes)
+  while (g.R > 2 && layout(g.R, false) > lds_bytes) g.R -= 2;
+  if (layout(g.R, false) > lds_bytes)
     return fail(err, HRT_ERR_UNSUPPORTED, "angle axis too long for the LDS row bands");
-  int grp3 = 1;
-  while (grp3 < (g.R + 4) / 2 && layout(g.R, grp3 + 1, false) <= lds_bytes) ++grp3;
-  layout(g.R, grp3, true);
+  layout(g.R, true);
   g.inplace_col = fft_fits_inplace(g.fft_r, 1, kColThreads);
   g.col_bytes = (g.inplace_col ? 1 : 2) * padded_len(g.Mr) * 8;
   if (g.col_bytes > lds_bytes + kBandStaticLds)
@@ -420,6 +413,25 @@ void place_data(const Geometry& g, int j, int k, double& xg, double& yg, double&
 double radon_row(const Geometry& g, int i, int l) {
   const double th = (g.d.tau0 + static_cast<double>(i) * g.d.dtau) / g.T;
   return std::log(g.qA[l] + g.qB[l] * th * th) / g.drho + g.crho;
+}
+
+// Cuts every band's list into ceil(n / max_entries) chunks of equal size
+// (a band with an empty list still gets one empty chunk).
+void make_chunks(int nb, int max_entries, BandLists& L) {
+  L.chunk_off.clear();
+  L.chunk_band.clear();
+  L.band_chunk.assign(nb + 1, 0);
+  for (int b = 0; b < nb; ++b) {
+    L.band_chunk[b] = static_cast<int32_t>(L.chunk_band.size());
+    const int64_t lo = L.off[b], n = L.off[b + 1] - lo;
+    const int64_t m = std::max<int64_t>(1, (n + max_entries - 1) / max_entries);
+    for (int64_t i = 0; i < m; ++i) {
+      L.chunk_off.push_back(lo + n * i / m);
+      L.chunk_band.push_back(b);
+    }
+  }
+  L.band_chunk[nb] = static_cast<int32_t>(L.chunk_band.size());
+  L.chunk_off.push_back(L.off[nb]);
 }
 
 // Band lists of one point set.  `place(p, xg, yg, w)` gives the coordinates
@@ -499,6 +511,8 @@ hrt_status build_lists(const Geometry& g, int64_t npts, PlaceF place, BandLists&
   auto ps = offsets(cs, spread);
   auto po = offsets(co, own);
   run(true, &ps, &po);
+  make_chunks(nb, kSpreadChunk, spread);
+  make_chunks(nb, kGatherChunk, own);
   return HRT_OK;
 }
 

@@ -24,6 +24,12 @@ constexpr int kBandThreads = 512;
 constexpr int kColThreads = 256;
 // The in-place FFT holds at most this many complex values per thread.
 constexpr int kInplaceValues = 16;
+// Point lists are cut into chunks of at most these many entries (spread:
+// each chunk writes one partial of its band's rows; gather: one workgroup),
+// and the spread stages kSpreadStage entries at a time in LDS.
+constexpr int kSpreadChunk = 8192;
+constexpr int kGatherChunk = 2048;
+constexpr int kSpreadStage = 1024;
 // Fraction bits of the log-radius coordinate in a point entry (the integer
 // part, the row relative to the band's first tap row, needs 3 bits).
 constexpr int kYFracBits = 28;
@@ -68,18 +74,16 @@ struct Geometry {
   int ctheta = 0, crho = 0;
   int u0 = 0, u1 = 0;         // lattice rows touched by any point [u0, u1)
   int R = 0, nbands = 0;      // row band height (even) and band count
-  int grp1 = 0, grp3 = 0;     // FFT scratch (sequences) of the band kernels
-  // FFTs in place (no LDS scratch; grp1 / grp3 sequences at a time): row FFT
-  // of the spread, row inverse FFT of the gather, column pass
-  bool inplace1 = false, inplace3 = false, inplace_col = false;
-  int xw0 = 0, W = 0;         // angle columns [xw0, xw0 + W) points can touch
+  // row FFTs (forward and inverse): in place `row_group` sequences at a
+  // time, or through an LDS scratch of `row_group` sequences at byte offset
+  // row_scratch (-1 when in place); the column FFT in place or not
+  int row_group = 0, row_scratch = -1;
+  bool inplace_col = false;
+  int xw0 = 0, W = 0;         // angle columns [xw0, xw0 + W) points can touch (W % 4 == 0)
   int x_frac_bits = 0;         // fraction bits of the angle coordinate in a point entry
-  // dynamic LDS of the band kernels: byte offset of the FFT scratch (the
-  // spread's fixed-point accumulator shares it; -1 when the FFT runs in
-  // place) and the total
-  int k1_acc = 0, k1_scratch = 0, k1_bytes = 0;
-  int k3_scratch = 0, k3_bytes = 0;
-  int col_bytes = 0;
+  // dynamic LDS per workgroup of the spread, row FFT, column and gather
+  // kernels
+  int spread_bytes = 0, row_bytes = 0, col_bytes = 0, gather_bytes = 0;
   int64_t n_kept = 0;
   std::vector<int32_t> jmin;  // [nx] first kept time sample of each trace
   // Radon side, per slowness l
@@ -111,6 +115,11 @@ struct PointEntry {
 struct BandLists {
   std::vector<PointEntry> e;
   std::vector<int64_t> off;
+  // the lists cut into chunks: chunk c covers e[chunk_off[c] .. chunk_off[c+1])
+  // of band chunk_band[c]; band b has chunks [band_chunk[b], band_chunk[b+1])
+  std::vector<int64_t> chunk_off;
+  std::vector<int32_t> chunk_band;
+  std::vector<int32_t> band_chunk;
 };
 
 struct PointTables {

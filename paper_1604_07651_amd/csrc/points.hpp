@@ -1,5 +1,5 @@
-// Point work of the band kernels: the fixed-point taps of the spread and the
-// 4x4 interpolation of the gather.
+// Point work of the spread: the fixed-point taps of one point, and a
+// workgroup maximum.
 #pragma once
 
 #include "device_common.hpp"
@@ -25,31 +25,6 @@ __device__ __forceinline__ void spread_taps(int* acc, int W, int nr, const Entry
 #pragma unroll
     for (int aa = 0; aa < 4; ++aa) atomicAdd(row + aa, __float2int_rn(wr * t.wx[aa]));
   }
-}
-
-// Sum of C[m, n] B3(x - m) B3(y - n) over the 4x4 taps of a point, C being
-// lattice rows held in LDS as complex pairs in the FFT's padded layout (held
-// row r at component r & 1 of pair r >> 1, pairs SP complex values apart,
-// rows [0, nheld)); `row0` is the held row of the first tap, `col0` the
-// lattice column of the first tap.  Taps outside the held rows are skipped
-// (no point a band owns reaches them with a non-zero weight).
-__device__ __forceinline__ float gather_taps(const float* ldsf, int SP, int nheld, int row0,
-                                             int col0, const float wx[4], const float wy[4]) {
-  int pc[4];
-#pragma unroll
-  for (int aa = 0; aa < 4; ++aa) pc[aa] = 2 * lpad(col0 + aa);
-  float acc = 0.0f;
-#pragma unroll
-  for (int bb = 0; bb < 4; ++bb) {
-    const int rl = row0 + bb;
-    if (rl < 0 || rl >= nheld) continue;
-    const float* base = ldsf + (rl >> 1) * SP * 2 + (rl & 1);
-    float row = 0.0f;
-#pragma unroll
-    for (int aa = 0; aa < 4; ++aa) row += base[pc[aa]] * wx[aa];
-    acc += row * wy[bb];
-  }
-  return acc;
 }
 
 // Maximum over the workgroup (kNtBand threads; s_wave holds kNtBand/64 floats).

@@ -93,8 +93,9 @@ class Plan:
         return self._call(self._lib.hrt_direct_adjoint, g, out, self.radon_shape,
                           self.data_shape, stream, "hrt_direct_adjoint")
 
-    STAGES = ("fwd_spread_rowfft", "fwd_colfft", "fwd_rowifft_gather",
-              "adj_spread_rowfft", "adj_colfft", "adj_rowifft_gather")
+    # kernels in the order of the library's profile slots
+    STAGES = ("fwd_spread", "fwd_rowfft", "fwd_colfft", "fwd_rowifft", "fwd_gather",
+              "adj_spread", "adj_rowfft", "adj_colfft", "adj_rowifft", "adj_gather")
 
     def profile_begin(self, max_records: int) -> None:
         """Start per-kernel HIP-event timing of forward/adjoint launches."""
@@ -103,8 +104,8 @@ class Plan:
 
     def profile_end(self) -> dict:
         """{stage: (summed ms, launches)} since profile_begin."""
-        ms = (C.c_double * 6)()
-        cnt = (C.c_int64 * 6)()
+        ms = (C.c_double * len(self.STAGES))()
+        cnt = (C.c_int64 * len(self.STAGES))()
         _lib.check(self._lib.hrt_profile_end(self._h, ms, cnt), "hrt_profile_end")
         return {name: (ms[i], cnt[i]) for i, name in enumerate(self.STAGES)}
 
