@@ -13,7 +13,7 @@ namespace hrt {
 
 constexpr int kNtBand = kBandThreads;  // threads of the band kernels
 constexpr int kNtCol = kColThreads;    // threads of the column kernel
-constexpr int kAbsMaxBlocks = 256;  // partial maxima of the input
+constexpr int kAbsMaxBlocks = 1024;  // partial maxima of the input
 
 // Everything the lattice kernels need about one plan (passed by value).
 struct DevGeo {
@@ -24,7 +24,7 @@ struct DevGeo {
   // row FFTs: sequences per group, byte offset of the LDS scratch (-1: in
   // place); the column FFT in place or not
   int row_group, row_scratch;
-  int col_inplace;
+  int col_inplace, col_batch;
   float knorm;                  // 1/(Mt Mr): both inverse FFTs are unnormalised
   float cmax_data, cmax_radon;  // bounds of the accumulated cells per unit input
   const int* jmin;              // first kept time sample of each trace

@@ -215,15 +215,15 @@ __device__ __forceinline__ unsigned div_magic(int d) {
 // One out-of-place radix-R Stockham pass over B sequences of length n:
 // src sequences at src + b*ss, results to dst + b*sd.  Ns is the length of
 // the sub-transforms already combined.  A thread takes U butterflies at a
-// time (U*R <= 16 values in registers) and issues all their loads before any
-// arithmetic, so that the LDS latencies overlap.  The twiddles w^r of a
+// time (as many as the in-place form holds) and issues all their loads before
+// any arithmetic, so that the LDS latencies overlap.  The twiddles w^r of a
 // butterfly are products of the table values w^(2^i), at most four factors.
 template <int R, int NT, bool INV>
 __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, int ss,
                                               float2* __restrict__ dst, int sd, int n,
                                               int B, int Ns,
                                               const float2* __restrict__ tw) {
-  constexpr int U = R >= 16 ? 1 : (R >= 8 ? 2 : (R >= 5 ? 3 : (R >= 4 ? 4 : (R >= 3 ? 5 : 8))));
+  constexpr int U = inplace_units(R, kInplaceValues) > 0 ? inplace_units(R, kInplaceValues) : 1;
   constexpr int NB2 = R > 8 ? 4 : (R > 4 ? 3 : (R > 2 ? 2 : 1));  // powers w^(2^i) needed
   const int nb = n / R;
   const int total = B * nb;
@@ -288,14 +288,14 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, in
 }
 
 // In-place form of the same pass for a batch small enough that every thread
-// can hold all of its butterflies at once (U*R <= kInplaceValues; the plan
-// checks ceil(B*n/R / NT) <= kInplaceValues/R for every radix): all loads, a
+// can hold all of its butterflies at once (U*R <= VALUES; the plan checks
+// ceil(B*n/R / NT) <= VALUES/R for every radix): all loads, a
 // barrier, then twiddles, DFTs and stores into the same buffer.  It needs no
 // scratch, so a workgroup takes half the LDS of the ping-pong form.
-template <int R, int NT, bool INV>
+template <int R, int NT, int VALUES, bool INV>
 __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, int B, int Ns,
                                              const float2* __restrict__ tw) {
-  constexpr int U = kInplaceValues / R;
+  constexpr int U = inplace_units(R, VALUES);
   constexpr int NB2 = R > 8 ? 4 : (R > 4 ? 3 : (R > 2 ? 2 : 1));
   const int nb = n / R;
   const int total = B * nb;
@@ -355,7 +355,7 @@ __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, in
 // Transform B sequences at data + b*stride in place, `group` sequences at a
 // time (see inplace_pass for the size condition on a group).  The caller
 // synchronises before the call; the call ends synchronised.
-template <int NT, bool INV>
+template <int NT, int VALUES, bool INV>
 __device__ void fft_inplace(float2* data, int stride, int B, int group, const FftDev& f,
                             const float2* __restrict__ tw) {
   const int n = f.n;
@@ -365,26 +365,27 @@ __device__ void fft_inplace(float2* data, int stride, int B, int group, const Ff
     int Ns = 1;
     for (int p = 0; p < f.npass; ++p) {
       switch (fft_radix(f, p)) {
-        case 16: inplace_pass<16, NT, INV>(a, stride, n, Bg, Ns, tw); break;
-        case 15: inplace_pass<15, NT, INV>(a, stride, n, Bg, Ns, tw); break;
-        case 12: inplace_pass<12, NT, INV>(a, stride, n, Bg, Ns, tw); break;
-        case 10: inplace_pass<10, NT, INV>(a, stride, n, Bg, Ns, tw); break;
-        case 9: inplace_pass<9, NT, INV>(a, stride, n, Bg, Ns, tw); break;
-        case 8: inplace_pass<8, NT, INV>(a, stride, n, Bg, Ns, tw); break;
-        case 6: inplace_pass<6, NT, INV>(a, stride, n, Bg, Ns, tw); break;
-        case 5: inplace_pass<5, NT, INV>(a, stride, n, Bg, Ns, tw); break;
-        case 4: inplace_pass<4, NT, INV>(a, stride, n, Bg, Ns, tw); break;
-        case 3: inplace_pass<3, NT, INV>(a, stride, n, Bg, Ns, tw); break;
-        default: inplace_pass<2, NT, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 16: inplace_pass<16, NT, VALUES, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 15: inplace_pass<15, NT, VALUES, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 12: inplace_pass<12, NT, VALUES, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 10: inplace_pass<10, NT, VALUES, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 9: inplace_pass<9, NT, VALUES, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 8: inplace_pass<8, NT, VALUES, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 6: inplace_pass<6, NT, VALUES, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 5: inplace_pass<5, NT, VALUES, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 4: inplace_pass<4, NT, VALUES, INV>(a, stride, n, Bg, Ns, tw); break;
+        case 3: inplace_pass<3, NT, VALUES, INV>(a, stride, n, Bg, Ns, tw); break;
+        default: inplace_pass<2, NT, VALUES, INV>(a, stride, n, Bg, Ns, tw); break;
       }
       Ns *= fft_radix(f, p);
     }
   }
 }
 
-// Either form: in place when `scratch` is null (`group` sequences at a time),
-// else ping-pong through `scratch` (room for `group` sequences).
-template <int NT, bool INV>
+// Either form: in place when `scratch` is null (`group` sequences at a time,
+// at most VALUES values per thread), else ping-pong through `scratch` (room
+// for `group` sequences).
+template <int NT, int VALUES, bool INV>
 __device__ __forceinline__ void fft_rows(float2* data, int stride, int B, float2* scratch,
                                          int group, const FftDev& f,
                                          const float2* __restrict__ tw);
@@ -446,11 +447,11 @@ __device__ __forceinline__ void load_twiddles(float2* s_tw, const float2* __rest
 }  // namespace hrt
 
 namespace hrt {
-template <int NT, bool INV>
+template <int NT, int VALUES, bool INV>
 __device__ __forceinline__ void fft_rows(float2* data, int stride, int B, float2* scratch,
                                          int group, const FftDev& f,
                                          const float2* __restrict__ tw) {
-  if (scratch == nullptr) fft_inplace<NT, INV>(data, stride, B, group, f, tw);
+  if (scratch == nullptr) fft_inplace<NT, VALUES, INV>(data, stride, B, group, f, tw);
   else fft_batch<NT, INV>(data, stride, B, scratch, group, f, tw);
 }
 }  // namespace hrt

@@ -411,6 +411,7 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
   G.xw0 = g.xw0; G.W = g.W; G.x_frac_bits = g.x_frac_bits;
   G.row_group = g.row_group; G.row_scratch = g.row_scratch;
   G.col_inplace = g.inplace_col ? 1 : 0;
+  G.col_batch = g.col_batch;
   G.knorm = static_cast<float>(1.0 / (static_cast<double>(g.Mt) * g.Mr));
   G.cmax_data = cmax_data;
   G.cmax_radon = cmax_radon;
@@ -473,6 +474,7 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const Geometry& g = p->g;
   const dim3 bands(g.nbands);
+  const dim3 cols((g.K1 + g.col_batch - 1) / g.col_batch);
   const size_t sb = g.spread_bytes, rb = g.row_bytes, cb = g.col_bytes, gb = g.gather_bytes;
   const int sl = adjoint ? kRadonSpread : kDataSpread;  // list spread
   const int gl = adjoint ? kDataOwn : kRadonOwn;        // list gathered at
@@ -499,9 +501,9 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
   {
     StageTimer t(p, st, t0 + 2);
     if (adjoint)
-      k_colfft<true><<<g.K1, kNtCol, cb, st>>>(p->dg, p->fr, p->tw_r, p->S, p->K);
+      k_colfft<true><<<cols, kNtCol, cb, st>>>(p->dg, p->fr, p->tw_r, p->S, p->K);
     else
-      k_colfft<false><<<g.K1, kNtCol, cb, st>>>(p->dg, p->fr, p->tw_r, p->S, p->K);
+      k_colfft<false><<<cols, kNtCol, cb, st>>>(p->dg, p->fr, p->tw_r, p->S, p->K);
   }
   {
     StageTimer t(p, st, t0 + 3);

@@ -31,15 +31,28 @@ namespace hrt {
 
 // Largest |x| over n floats as kAbsMaxBlocks partial maxima (no atomics and
 // nothing to clear, so replays are safe); a non-finite input makes its block
-// report +inf.
+// report +inf.  16-byte loads when x is 16-byte aligned.
 __global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ x, int64_t n,
                                                 float* __restrict__ partial) {
   __shared__ float s_m[4];
   float m = 0.0f;
   bool bad = false;
+  const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += stride) {
+  int64_t done = 0;
+  if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    const int64_t n4 = n / 4;
+    for (int64_t i = tid; i < n4; i += stride) {
+      const float4 v = x4[i];
+      const float a = fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w)));
+      bad |= !(fabsf(v.x) <= 3.0e38f && fabsf(v.y) <= 3.0e38f && fabsf(v.z) <= 3.0e38f &&
+               fabsf(v.w) <= 3.0e38f);
+      m = fmaxf(m, a);
+    }
+    done = 4 * n4;
+  }
+  for (int64_t i = done + tid; i < n; i += stride) {
     const float v = fabsf(x[i]);
     bad |= !(v <= 3.0e38f);
     m = fmaxf(m, v);
@@ -128,7 +141,7 @@ __global__ __launch_bounds__(kNtBand) void k_spread(
 // complex pair p, FFT along the angle, and the k1 < K1 half spectrum of both
 // rows to S.  Dynamic LDS: the pairs, then the FFT scratch (if any).
 template <int MODE>
-__global__ __launch_bounds__(kNtBand) void k_rowfft(
+__global__ __launch_bounds__(kNtBand, 6) void k_rowfft(
     DevGeo G, FftDev F, const float2* __restrict__ tw, const float* __restrict__ absmax,
     const int* __restrict__ Hp, const int* __restrict__ band_chunk, float2* __restrict__ S) {
   extern __shared__ float2 lds[];
@@ -165,7 +178,7 @@ __global__ __launch_bounds__(kNtBand) void k_rowfft(
     lds[p * SP + lpad(m)] = make_float2(lo + bad, hi + bad);
   }
   __syncthreads();
-  fft_rows<kNtBand, false>(lds, SP, npair, fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
+  fft_rows<kNtBand, kInplaceValues, false>(lds, SP, npair, fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
                            G.row_group, F, s_tw);
   // two real rows per complex sequence: X1 = (Z[k] + conj Z[-k])/2,
   // X2 = (Z[k] - conj Z[-k])/(2i); keep k1 < K1
@@ -180,44 +193,57 @@ __global__ __launch_bounds__(kNtBand) void k_rowfft(
   }
 }
 
+// Column pass: col_batch kept k1 columns per workgroup: FFT along the log
+// radius, multiply by K (conj K for the adjoint; K(k1, -k2) = conj K(k1, k2)),
+// normalise, inverse FFT; only the used rows [u0, u1) come from and go back
+// to S.  Dynamic LDS: the columns, then the FFT scratch (if any).
 template <bool ADJ>
-__global__ __launch_bounds__(kNtCol) void k_colfft(DevGeo G, FftDev F,
+__global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo G, FftDev F,
                                                    const float2* __restrict__ tw,
                                                    float2* __restrict__ S,
                                                    const float2* __restrict__ K) {
   extern __shared__ float2 lds[];
   __shared__ float2 s_tw[kTwLds];
   load_twiddles<kNtCol>(s_tw, tw, G.Mr);
-  const int k1 = blockIdx.x;
+  const int c0 = blockIdx.x * G.col_batch;
+  const int nc = min(G.col_batch, G.K1 - c0);
   const int Mr = G.Mr, SP = padded_len(G.Mr);
-  float2* col = S + static_cast<size_t>(k1) * Mr;
-  for (int n = threadIdx.x; n < Mr; n += kNtCol)
-    lds[lpad(n)] = (n >= G.u0 && n < G.u1) ? col[n] : make_float2(0.f, 0.f);
+  for (int i = threadIdx.x; i < nc * Mr; i += kNtCol) {
+    const int c = i / Mr;
+    const int n = i - c * Mr;
+    lds[c * SP + lpad(n)] = (n >= G.u0 && n < G.u1) ? S[static_cast<size_t>(c0 + c) * Mr + n]
+                                                    : make_float2(0.f, 0.f);
+  }
   __syncthreads();
   float2* cscr = G.col_inplace ? nullptr : lds + SP;
-  fft_rows<kNtCol, false>(lds, SP, 1, cscr, 1, F, s_tw);
-  const float2* Kr = K + static_cast<size_t>(k1) * G.K2;
-  for (int n = threadIdx.x; n < Mr; n += kNtCol) {
+  fft_rows<kNtCol, kInplaceValues, false>(lds, SP, nc, cscr, nc, F, s_tw);
+  for (int i = threadIdx.x; i < nc * Mr; i += kNtCol) {
+    const int c = i / Mr;
+    const int n = i - c * Mr;
     const int k = (n < Mr / 2) ? n : n - Mr;
     const int ak = k < 0 ? -k : k;
     float2 v = make_float2(0.f, 0.f);
     if (ak < G.K2) {
-      float2 kv = Kr[ak];
-      // K(k1, -k2) = conj K(k1, k2); the adjoint uses conj K
+      float2 kv = K[static_cast<size_t>(c0 + c) * G.K2 + ak];
       if ((k < 0) != ADJ) kv.y = -kv.y;
-      v = cscale(cmul(lds[lpad(n)], kv), G.knorm);
+      v = cscale(cmul(lds[c * SP + lpad(n)], kv), G.knorm);
     }
-    lds[lpad(n)] = v;
+    lds[c * SP + lpad(n)] = v;
   }
   __syncthreads();
-  fft_rows<kNtCol, true>(lds, SP, 1, cscr, 1, F, s_tw);
-  for (int n = G.u0 + threadIdx.x; n < G.u1; n += kNtCol) col[n] = lds[lpad(n)];
+  fft_rows<kNtCol, kInplaceValues, true>(lds, SP, nc, cscr, nc, F, s_tw);
+  const int U = G.u1 - G.u0;
+  for (int i = threadIdx.x; i < nc * U; i += kNtCol) {
+    const int c = i / U;
+    const int n = G.u0 + (i - c * U);
+    S[static_cast<size_t>(c0 + c) * Mr + n] = lds[c * SP + lpad(n)];
+  }
 }
 
 // Inverse row FFT of one band: Z = X1 + i X2 for rows (2p, 2p+1) with the
 // Hermitian completion Z[-k], inverse FFT along the angle, real rows to Cr
 // (window columns only).  Dynamic LDS: the pairs, then the FFT scratch.
-__global__ __launch_bounds__(kNtBand) void k_rowifft(DevGeo G, FftDev F,
+__global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo G, FftDev F,
                                                      const float2* __restrict__ tw,
                                                      const float2* __restrict__ S,
                                                      float* __restrict__ Cr) {
@@ -241,7 +267,7 @@ __global__ __launch_bounds__(kNtBand) void k_rowifft(DevGeo G, FftDev F,
     if (k > 0) lds[p * SP + lpad(Mt - k)] = make_float2(x.x + x.w, x.z - x.y);
   }
   __syncthreads();
-  fft_rows<kNtBand, true>(lds, SP, npair, fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
+  fft_rows<kNtBand, kInplaceValues, true>(lds, SP, npair, fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
                           G.row_group, F, s_tw);
   float* dst = Cr + static_cast<size_t>(n0 - G.u0) * W;
   for (int idx = threadIdx.x; idx < npair * W; idx += kNtBand) {

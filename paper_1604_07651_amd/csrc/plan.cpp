@@ -44,12 +44,12 @@ struct TraceScan {
 
 }  // namespace
 
-bool fft_fits_inplace(const FftFactors& f, int batch, int threads) {
+bool fft_fits_inplace(const FftFactors& f, int batch, int threads, int values) {
   if (f.npass < 1) return false;
   for (int p = 0; p < f.npass; ++p) {
     const int64_t r = f.radix[p];
     const int64_t bfly = static_cast<int64_t>(batch) * f.n / r;
-    if ((bfly + threads - 1) / threads > kInplaceValues / r) return false;
+    if ((bfly + threads - 1) / threads > inplace_units(static_cast<int>(r), values)) return false;
   }
   return true;
 }
@@ -357,7 +357,7 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   auto inplace_group = [&](int B) {
     int grp = 0;
     for (int b = 1; b <= B; ++b)
-      if (fft_fits_inplace(g.fft_t, b, kBandThreads)) grp = b;
+      if (fft_fits_inplace(g.fft_t, b, kBandThreads, kInplaceValues)) grp = b;
     return grp;
   };
   auto layout = [&](int R, bool commit) {
@@ -380,8 +380,11 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   if (layout(g.R, false) > lds_bytes)
     return fail(err, HRT_ERR_UNSUPPORTED, "angle axis too long for the LDS row bands");
   layout(g.R, true);
-  g.inplace_col = fft_fits_inplace(g.fft_r, 1, kColThreads);
-  g.col_bytes = (g.inplace_col ? 1 : 2) * padded_len(g.Mr) * 8;
+  // one column per workgroup: two per workgroup (fewer, fuller
+  // workgroups) measured slower at C3, the column pass being short of waves
+  g.col_batch = 1;
+  g.inplace_col = fft_fits_inplace(g.fft_r, g.col_batch, kColThreads, kInplaceValues);
+  g.col_bytes = (g.inplace_col ? g.col_batch : 2) * padded_len(g.Mr) * 8;
   if (g.col_bytes > lds_bytes + kBandStaticLds)
     return fail(err, HRT_ERR_UNSUPPORTED, "log-radius axis too long for an LDS column");
   g.nbands = (g.u1 - g.u0 + g.R - 1) / g.R;

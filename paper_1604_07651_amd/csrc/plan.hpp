@@ -41,11 +41,16 @@ constexpr int kYFracBits = 28;
 constexpr int lpad(int e) { return e; }
 constexpr int padded_len(int n) { return n; }
 
+// Butterflies a thread holds in an in-place radix-R pass with at most
+// `values` complex values per thread (capped at 2 to bound the registers of
+// small radices).
+constexpr int inplace_units(int R, int values) { return values / R < 2 ? values / R : 2; }
+
 // True when the in-place FFT can hold all butterflies of `batch` sequences
 // of f.n points with `threads` threads: ceil(batch*n/R / threads) <=
-// kInplaceValues/R for every radix R of f.
+// inplace_units(R, values) for every radix R of f.
 struct FftFactors;
-bool fft_fits_inplace(const FftFactors& f, int batch, int threads);
+bool fft_fits_inplace(const FftFactors& f, int batch, int threads, int values);
 
 // Mixed-radix factorisation of an FFT length (radices of kFftRadices).
 struct FftFactors {
@@ -79,6 +84,7 @@ struct Geometry {
   // row_scratch (-1 when in place); the column FFT in place or not
   int row_group = 0, row_scratch = -1;
   bool inplace_col = false;
+  int col_batch = 1;          // columns per workgroup of the column kernel
   int xw0 = 0, W = 0;         // angle columns [xw0, xw0 + W) points can touch (W % 4 == 0)
   int x_frac_bits = 0;         // fraction bits of the angle coordinate in a point entry
   // dynamic LDS per workgroup of the spread, row FFT, column and gather
