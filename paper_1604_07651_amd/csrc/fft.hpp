@@ -303,7 +303,7 @@ __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, in
   const int nhi = (n + 63) >> 6;
   const unsigned m_nb = div_magic(nb), m_ns = div_magic(Ns);
   float2 v[U][R];
-  int ob[U], kk[U];
+  int ob[U], oo[U], kk[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int idx = threadIdx.x + u * NT;
@@ -311,7 +311,8 @@ __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, in
     const int j = idx - b * nb;
     const int k = j - div_small(j, m_ns) * Ns;
     kk[u] = k;
-    ob[u] = b * stride + (j - k) * R + k;
+    ob[u] = b * stride;
+    oo[u] = (j - k) * R + k;
     if (idx < total) {
       const float2* in = data + b * stride;
 #pragma unroll
@@ -346,7 +347,7 @@ __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, in
       }
       Dft<R, INV>::run(v[u]);
 #pragma unroll
-      for (int r = 0; r < R; ++r) data[lpad(ob[u] + r * Ns)] = v[u][r];
+      for (int r = 0; r < R; ++r) data[ob[u] + lpad(oo[u] + r * Ns)] = v[u][r];
     }
   }
   __syncthreads();

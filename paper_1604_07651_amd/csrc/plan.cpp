@@ -54,7 +54,7 @@ bool fft_fits_inplace(const FftFactors& f, int batch, int threads, int values) {
   return true;
 }
 
-FftFactors factor_fft(int n) {
+FftFactors factor_fft(int n, int max_radix) {
   FftFactors f;
   f.n = n;
   int m = n;
@@ -66,7 +66,7 @@ FftFactors factor_fft(int n) {
   m = n;
   while (m > 1) {
     for (int r : kFftRadices) {
-      if (m % r == 0) {
+      if (r <= max_radix && m % r == 0) {
         if (f.npass < kMaxPasses) f.radix[f.npass] = r;
         ++f.npass;
         m /= r;

@@ -35,11 +35,11 @@ constexpr int kSpreadStage = 1024;
 constexpr int kYFracBits = 28;
 
 // LDS layout of the FFT sequences: element e of a sequence sits at slot
-// lpad(e), and a sequence of n elements takes padded_len(n) slots.  (Padding
-// these, one unused slot per 16 elements against bank conflicts of the
-// strided passes, measured slower: the larger footprint costs occupancy.)
-constexpr int lpad(int e) { return e; }
-constexpr int padded_len(int n) { return n; }
+// lpad(e) = e + e/16, so that the stores of the early passes, R*Ns complex
+// values apart, spread over the LDS banks instead of piling onto a few; a
+// sequence of n elements takes padded_len(n) slots.
+constexpr int lpad(int e) { return e + (e >> 4); }
+constexpr int padded_len(int n) { return n + (n >> 4) + 2; }
 
 // Butterflies a thread holds in an in-place radix-R pass with at most
 // `values` complex values per thread (capped at 2 to bound the registers of
@@ -59,7 +59,8 @@ struct FftFactors {
   int radix[kMaxPasses] = {};
 };
 
-FftFactors factor_fft(int n);
+// Radices are taken largest first from kFftRadices, up to max_radix.
+FftFactors factor_fft(int n, int max_radix = 16);
 
 // Everything the plan derives from the grids (Sections 2.1, 2.2, 4).
 struct Geometry {
