@@ -121,6 +121,44 @@ hrt_status hrt_direct_forward(hrt_plan_t plan, const float* f, float* g,
 hrt_status hrt_direct_adjoint(hrt_plan_t plan, const float* g, float* f,
                               void* stream);
 
+/* Soft-thresholding iterations for sparse Radon representations and trace
+ * interpolation (Section 3, eq. itersmd):
+ *   g <- S_{c2 mu}(g + c2 R_h(f - chi_S R_h^T g)),
+ * S_mu(v) = v - mu/2 for v >= mu/2, 0 for |v| < mu/2, v + mu/2 for
+ * v <= -mu/2.  f float32[nx][nt] is the recorded gather (0 where traces are
+ * missing); mask float32[nx][nt] is chi_S (1 where recorded, 0 where missing;
+ * NULL: everything recorded, which is eq. iters); g float32[nq][ntau] is the
+ * Radon panel, updated in place `iters` times.  work_data float32[nx][nt] and
+ * work_radon float32[nq][ntau] are caller-owned scratch.  c2 > 0 is the step
+ * c^2 (convergence needs c2 * ||R_h||^2 < 1, see hrt_opnorm2), mu >= 0 the
+ * sparsity weight.  Enqueues only (no allocation, no host synchronization),
+ * so it may be captured in a HIP graph.  All arrays device pointers; none
+ * may overlap another. */
+hrt_status hrt_ista_iterate(hrt_plan_t plan, const float* f, const float* mask, float* g,
+                            float* work_data, float* work_radon, int32_t iters, float c2,
+                            float mu, void* stream);
+
+/* The same iterations captured once into an executable HIP graph (the
+ * arrays are bound at capture; replays reuse them).  Allocates the graph;
+ * launch with hrt_graph_launch on any stream, release with
+ * hrt_graph_destroy.  Not while a profile (hrt_profile_begin) is active. */
+typedef struct hrt_graph_s* hrt_graph_t;
+hrt_status hrt_ista_graph_create(hrt_plan_t plan, const float* f, const float* mask,
+                                 float* g, float* work_data, float* work_radon,
+                                 int32_t iters, float c2, float mu, hrt_graph_t* out);
+hrt_status hrt_graph_launch(hrt_graph_t graph, void* stream);
+void hrt_graph_destroy(hrt_graph_t graph);
+
+/* ||R_h||^2, the largest eigenvalue of R_h^T R_h, by `iters` steps of the
+ * power iteration from a start vector drawn from `seed` (splitmix64,
+ * uniform in [-1, 1)): v <- R^T R v / ||R^T R v||, estimate <v, R^T R v>
+ * with |v| = 1.  The operators run in float32, every inner product and norm
+ * is accumulated in float64.  work_data, work_data2 float32[nx][nt] and
+ * work_radon float32[nq][ntau] are caller-owned scratch.  Synchronizes the
+ * stream at every step; writes the estimate to *out (host). */
+hrt_status hrt_opnorm2(hrt_plan_t plan, int32_t iters, uint64_t seed, float* work_data,
+                       float* work_data2, float* work_radon, double* out, void* stream);
+
 /* Copy of the plan's summary. */
 hrt_status hrt_query(hrt_plan_t plan, hrt_info* out);
 

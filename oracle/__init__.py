@@ -22,4 +22,4 @@ zeta by quadrature), `ista` (soft-thresholding iterations of Section 3).
 All arithmetic is float64.  Readings of points where the paper is silent or
 garbled are stated in each function's docstring.
 """
-from . import bspline, geometry, kernel, logpolar, direct  # noqa: F401
+from . import bspline, geometry, kernel, logpolar, direct, ista  # noqa: F401

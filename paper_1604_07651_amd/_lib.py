@@ -48,6 +48,16 @@ SIGNATURES = [
     ("hrt_profile_begin", C.c_int, [C.c_void_p, C.c_int32]),
     ("hrt_profile_end", C.c_int, [C.c_void_p, C.POINTER(C.c_double),
                                   C.POINTER(C.c_int64)]),
+    ("hrt_ista_iterate", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                                   C.c_float, C.c_void_p]),
+    ("hrt_ista_graph_create", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                                        C.c_float, C.POINTER(C.c_void_p)]),
+    ("hrt_graph_launch", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("hrt_graph_destroy", None, [C.c_void_p]),
+    ("hrt_opnorm2", C.c_int, [C.c_void_p, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     ("hrt_plan_destroy", None, [C.c_void_p]),
     ("hrt_status_string", C.c_char_p, [C.c_int]),
     ("hrt_last_error", C.c_char_p, []),

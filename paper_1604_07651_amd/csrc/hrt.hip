@@ -25,10 +25,12 @@
 #include "hrt.h"
 #include "lp_kernels.hpp"
 #include "plan.hpp"
+#include "ista_kernels.hpp"
 #include "plan_kernels.hpp"
 
 namespace hrt {
 constexpr uint64_t kMagic = 0x6872745f706c616eull;
+constexpr uint64_t kGraphMagic = 0x6872745f67726170ull;
 static_assert(kTwLds * sizeof(float2) + kNtBand / 64 * sizeof(float) <= kBandStaticLds,
               "static LDS");
 static_assert(sizeof(PointEntry) == sizeof(uint4), "point entry layout");
@@ -62,6 +64,7 @@ struct hrt_plan_s {
   int* Hp = nullptr;        // partial fixed-point rows of the spread chunks
   float* Cr = nullptr;      // real lattice rows after the inverse row FFT
   float* absmax = nullptr;  // kAbsMaxBlocks partial maxima of the current input
+  double* dot = nullptr;    // kDotBlocks partial sums of the power iteration
   // per-kernel timing (hrt_profile_begin / hrt_profile_end)
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_stage;
@@ -130,7 +133,7 @@ hrt_status upload(T* dst, const std::vector<T>& src) {
 }
 
 void free_plan(hrt_plan_s* p) {
-  void* ptrs[] = {p->S, p->K, p->tw_t, p->tw_r, p->jmin, p->absmax, p->Hp, p->Cr};
+  void* ptrs[] = {p->S, p->K, p->tw_t, p->tw_r, p->jmin, p->absmax, p->Hp, p->Cr, p->dot};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int i = 0; i < 4; ++i) {
@@ -288,6 +291,7 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
       (s = dev_alloc(&p->tw_r, twr.size(), total)) ||
       (s = dev_alloc(&p->jmin, g.d.nx, total)) ||
       (s = dev_alloc(&p->absmax, kAbsMaxBlocks, total)) ||
+      (s = dev_alloc(&p->dot, kDotBlocks, total)) ||
       (s = upload(p->tw_t, twt)) || (s = upload(p->tw_r, twr)) ||
       (s = upload(p->jmin, g.jmin))) {
     free_plan(p);
@@ -529,6 +533,165 @@ hrt_status hrt_forward(hrt_plan_t p, const float* f, float* g, void* stream) {
 
 hrt_status hrt_adjoint(hrt_plan_t p, const float* g, float* f, void* stream) {
   return launch_chain(p, g, f, stream, true);
+}
+
+namespace {
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + nb && y < x + na;
+}
+
+int vec_blocks(int64_t n) {
+  return static_cast<int>(std::min<int64_t>(2048, std::max<int64_t>(1, (n + kVecThreads - 1) / kVecThreads)));
+}
+}  // namespace
+
+hrt_status hrt_ista_iterate(hrt_plan_t p, const float* f, const float* mask, float* g,
+                            float* work_data, float* work_radon, int32_t iters, float c2,
+                            float mu, void* stream) {
+  hrt_status s = check_plan(p);
+  if (s != HRT_OK) return s;
+  if (!f || !g || !work_data || !work_radon) return set_err(HRT_ERR_INVALID_ARG, "null array");
+  if (iters < 0 || !(c2 > 0.0f) || !(mu >= 0.0f))
+    return set_err(HRT_ERR_INVALID_ARG, "need iters >= 0, c2 > 0, mu >= 0");
+  const size_t nd = static_cast<size_t>(p->g.d.nx) * p->g.d.nt * sizeof(float);
+  const size_t nr = static_cast<size_t>(p->g.d.nq) * p->g.d.ntau * sizeof(float);
+  if (overlaps(g, nr, work_radon, nr) || overlaps(g, nr, work_data, nd) ||
+      overlaps(g, nr, f, nd) || overlaps(work_data, nd, work_radon, nr) ||
+      overlaps(work_data, nd, f, nd) || overlaps(work_radon, nr, f, nd) ||
+      (mask && (overlaps(mask, nd, work_data, nd) || overlaps(mask, nd, g, nr) ||
+                overlaps(mask, nd, work_radon, nr))))
+    return set_err(HRT_ERR_INVALID_ARG, "arrays overlap");
+  DeviceGuard guard(p->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t n_data = static_cast<int64_t>(p->g.d.nx) * p->g.d.nt;
+  const int64_t n_radon = static_cast<int64_t>(p->g.d.nq) * p->g.d.ntau;
+  for (int it = 0; it < iters; ++it) {
+    if ((s = launch_chain(p, g, work_data, stream, true)) != HRT_OK) return s;
+    k_residual<<<vec_blocks(n_data), kVecThreads, 0, st>>>(f, mask, work_data, n_data);
+    if ((s = launch_chain(p, work_data, work_radon, stream, false)) != HRT_OK) return s;
+    k_soft_update<<<vec_blocks(n_radon), kVecThreads, 0, st>>>(g, work_radon, c2,
+                                                               0.5f * c2 * mu, n_radon);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(e, "ista launch");
+  return HRT_OK;
+}
+
+struct hrt_graph_s {
+  uint64_t magic;
+  int device;
+  hipGraphExec_t exec;
+};
+
+hrt_status hrt_ista_graph_create(hrt_plan_t p, const float* f, const float* mask, float* g,
+                                 float* work_data, float* work_radon, int32_t iters, float c2,
+                                 float mu, hrt_graph_t* out) {
+  hrt_status s = check_plan(p);
+  if (s != HRT_OK) return s;
+  if (!out) return set_err(HRT_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (!p->prof_ev.empty()) return set_err(HRT_ERR_INVALID_ARG, "profiling is active");
+  DeviceGuard guard(p->device);
+  hipStream_t cs = nullptr;
+  HRT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return hip_err(e, "hipStreamBeginCapture");
+  }
+  s = hrt_ista_iterate(p, f, mask, g, work_data, work_radon, iters, c2, mu, cs);
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (s != HRT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return hip_err(e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_err(e, "hipGraphInstantiate");
+  auto* gr = new hrt_graph_s{kGraphMagic, p->device, exec};
+  *out = gr;
+  return HRT_OK;
+}
+
+hrt_status hrt_graph_launch(hrt_graph_t gr, void* stream) {
+  if (!gr || gr->magic != kGraphMagic) return set_err(HRT_ERR_BAD_HANDLE, "bad graph handle");
+  DeviceGuard guard(gr->device);
+  HRT_HIP(hipGraphLaunch(gr->exec, reinterpret_cast<hipStream_t>(stream)), "hipGraphLaunch");
+  return HRT_OK;
+}
+
+void hrt_graph_destroy(hrt_graph_t gr) {
+  if (!gr || gr->magic != kGraphMagic) return;
+  DeviceGuard guard(gr->device);
+  (void)hipDeviceSynchronize();
+  (void)hipGraphExecDestroy(gr->exec);
+  gr->magic = 0;
+  delete gr;
+}
+
+hrt_status hrt_opnorm2(hrt_plan_t p, int32_t iters, uint64_t seed, float* work_data,
+                       float* work_data2, float* work_radon, double* out, void* stream) {
+  hrt_status s = check_plan(p);
+  if (s != HRT_OK) return s;
+  if (!work_data || !work_data2 || !work_radon || !out || iters < 1)
+    return set_err(HRT_ERR_INVALID_ARG, "null array or iters < 1");
+  const int64_t n_data = static_cast<int64_t>(p->g.d.nx) * p->g.d.nt;
+  const size_t nd = static_cast<size_t>(n_data) * sizeof(float);
+  const size_t nr = static_cast<size_t>(p->g.d.nq) * p->g.d.ntau * sizeof(float);
+  if (overlaps(work_data, nd, work_data2, nd) || overlaps(work_data, nd, work_radon, nr) ||
+      overlaps(work_data2, nd, work_radon, nr))
+    return set_err(HRT_ERR_INVALID_ARG, "arrays overlap");
+  DeviceGuard guard(p->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // seeded start vector (splitmix64 -> uniform in [-1, 1))
+  std::vector<float> v0(static_cast<size_t>(n_data));
+  uint64_t z = seed;
+  for (float& x : v0) {
+    z += 0x9e3779b97f4a7c15ull;
+    uint64_t t = z;
+    t = (t ^ (t >> 30)) * 0xbf58476d1ce4e5b9ull;
+    t = (t ^ (t >> 27)) * 0x94d049bb133111ebull;
+    t ^= t >> 31;
+    x = static_cast<float>(static_cast<double>(t >> 11) * 0x1.0p-52 - 1.0);
+  }
+  HRT_HIP(hipMemcpyAsync(work_data, v0.data(), nd, hipMemcpyHostToDevice, st), "upload start");
+  std::vector<double> part(kDotBlocks);
+  auto dot = [&](const float* a, const float* b, double& r) -> hrt_status {
+    k_dot64<<<kDotBlocks, kVecThreads, 0, st>>>(a, b, n_data, p->dot);
+    HRT_HIP(hipMemcpyAsync(part.data(), p->dot, kDotBlocks * sizeof(double),
+                           hipMemcpyDeviceToHost, st),
+            "read partial sums");
+    HRT_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    r = 0.0;
+    for (double x : part) r += x;
+    return HRT_OK;
+  };
+  double vv = 0.0, lambda = 0.0;
+  if ((s = dot(work_data, work_data, vv)) != HRT_OK) return s;
+  k_scale<<<vec_blocks(n_data), kVecThreads, 0, st>>>(work_data, work_data, 1.0 / std::sqrt(vv),
+                                                       n_data);
+  for (int it = 0; it < iters; ++it) {
+    // w = R* R v, lambda = <v, w> for |v| = 1, then v = w / |w|
+    if ((s = launch_chain(p, work_data, work_radon, stream, false)) != HRT_OK) return s;
+    if ((s = launch_chain(p, work_radon, work_data2, stream, true)) != HRT_OK) return s;
+    double vw = 0.0, ww = 0.0;
+    if ((s = dot(work_data, work_data2, vw)) != HRT_OK) return s;
+    if ((s = dot(work_data2, work_data2, ww)) != HRT_OK) return s;
+    lambda = vw;
+    if (!(ww > 0.0)) break;
+    k_scale<<<vec_blocks(n_data), kVecThreads, 0, st>>>(work_data, work_data2,
+                                                         1.0 / std::sqrt(ww), n_data);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(e, "power iteration");
+  *out = lambda;
+  return HRT_OK;
 }
 
 hrt_status hrt_direct_forward(hrt_plan_t p, const float* f, float* g, void* stream) {

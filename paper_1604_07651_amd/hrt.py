@@ -119,6 +119,102 @@ class Plan:
         return out[..., 0] + 1j * out[..., 1]
 
 
+    # --- soft-thresholding iterations (Section 3, eqs. iters / itersmd) ---
+
+    def _work(self, work):
+        if work is None:
+            work = (torch.empty(self.data_shape, device=self.device),
+                    torch.empty(self.radon_shape, device=self.device))
+        self._check_in(work[0], self.data_shape, "work_data")
+        self._check_in(work[1], self.radon_shape, "work_radon")
+        return work
+
+    def _ista_args(self, f, mask, g):
+        self._check_in(f, self.data_shape, "f")
+        self._check_in(g, self.radon_shape, "g")
+        if mask is not None:
+            self._check_in(mask, self.data_shape, "mask")
+        return C.c_void_p(mask.data_ptr()) if mask is not None else None
+
+    def ista_iterate(self, f, g, iters: int, c2: float, mu: float, mask=None, work=None,
+                     stream=None) -> torch.Tensor:
+        """`iters` steps of g <- S_{c2 mu}(g + c2 R(f - mask R^T g)), in place on g."""
+        m = self._ista_args(f, mask, g)
+        wd, wr = self._work(work)
+        _lib.check(self._lib.hrt_ista_iterate(
+            self._h, C.c_void_p(f.data_ptr()), m, C.c_void_p(g.data_ptr()),
+            C.c_void_p(wd.data_ptr()), C.c_void_p(wr.data_ptr()), int(iters), float(c2),
+            float(mu), _stream_handle(stream)), "hrt_ista_iterate")
+        return g
+
+    def ista_graph(self, f, g, iters: int, c2: float, mu: float, mask=None, work=None):
+        """The same iterations captured in a HIP graph; returns an IstaGraph
+        whose launch() replays them on the bound arrays."""
+        m = self._ista_args(f, mask, g)
+        wd, wr = self._work(work)
+        handle = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.hrt_ista_graph_create(
+                self._h, C.c_void_p(f.data_ptr()), m, C.c_void_p(g.data_ptr()),
+                C.c_void_p(wd.data_ptr()), C.c_void_p(wr.data_ptr()), int(iters), float(c2),
+                float(mu), C.byref(handle)), "hrt_ista_graph_create")
+        return IstaGraph(self._lib, handle, (f, mask, g, wd, wr))
+
+    def opnorm2(self, iters: int = 30, seed: int = 0, stream=None) -> float:
+        """||R||^2 by float64 power iteration on R^T R."""
+        wd = torch.empty(self.data_shape, device=self.device)
+        wd2 = torch.empty(self.data_shape, device=self.device)
+        wr = torch.empty(self.radon_shape, device=self.device)
+        out = C.c_double()
+        _lib.check(self._lib.hrt_opnorm2(self._h, int(iters), C.c_uint64(seed),
+                                         C.c_void_p(wd.data_ptr()), C.c_void_p(wd2.data_ptr()),
+                                         C.c_void_p(wr.data_ptr()), C.byref(out),
+                                         _stream_handle(stream)), "hrt_opnorm2")
+        return out.value
+
+
+class IstaGraph:
+    """An executable HIP graph of soft-thresholding iterations (keeps the
+    arrays it was captured on alive)."""
+
+    def __init__(self, lib, handle, arrays):
+        self._lib, self._h, self._arrays = lib, handle, arrays
+
+    def launch(self, stream=None) -> None:
+        _lib.check(self._lib.hrt_graph_launch(self._h, _stream_handle(stream)),
+                   "hrt_graph_launch")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.hrt_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ista(plan: Plan, f: torch.Tensor, mask=None, iters: int = 100, mu: float = 0.0,
+         c2=None, graph: bool = True, g0=None) -> torch.Tensor:
+    """Sparse Radon panel g of a gather f with missing traces (mask = 1 where
+    recorded) by `iters` soft-thresholding iterations of eq. itersmd; the
+    step c2 defaults to 0.99 / ||R||^2 (float64 power iteration).  Returns g;
+    the interpolated gather is plan.adjoint(g)."""
+    if c2 is None:
+        c2 = 0.99 / plan.opnorm2()
+    g = torch.zeros(plan.radon_shape, device=plan.device) if g0 is None else g0.clone()
+    if graph:
+        gr = plan.ista_graph(f, g, iters, c2, mu, mask)
+        gr.launch()
+        torch.cuda.current_stream().synchronize()
+        gr.close()
+    else:
+        plan.ista_iterate(f, g, iters, c2, mu, mask)
+    return g
+
+
 class HRTFunction(torch.autograd.Function):
     """g = R_h f with backward grad_f = R_h^T grad_g (R_h is linear)."""
 

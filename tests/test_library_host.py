@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     text = open(os.path.join(ROOT, "include", "hrt.h")).read()
-    return sorted(set(re.findall(r"\b(hrt_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(hrt_[a-z_0-9]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
