@@ -175,10 +175,10 @@ hrt_status hrt_plan_kernel(hrt_plan_t plan, float* host_out);
  * have been recorded.  hrt_profile_end synchronizes on the recorded events,
  * writes the summed milliseconds and the launch count per kernel into
  * ms_sum[HRT_PROFILE_SLOTS] and count[HRT_PROFILE_SLOTS] (order: forward
- * spread (with the input maximum), row FFT, column pass, row inverse FFT,
- * gather, then the same five of the adjoint) and releases the events.
- * Either output may be NULL. */
-#define HRT_PROFILE_SLOTS 10
+ * input maximum, spread, row FFT, column pass, row inverse FFT, gather, then
+ * the same six of the adjoint) and releases the events.  Either output may
+ * be NULL. */
+#define HRT_PROFILE_SLOTS 12
 hrt_status hrt_profile_begin(hrt_plan_t plan, int32_t max_records);
 hrt_status hrt_profile_end(hrt_plan_t plan, double* ms_sum, int64_t* count);
 

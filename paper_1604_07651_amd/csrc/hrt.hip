@@ -482,10 +482,13 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
   const size_t sb = g.spread_bytes, rb = g.row_bytes, cb = g.col_bytes, gb = g.gather_bytes;
   const int sl = adjoint ? kRadonSpread : kDataSpread;  // list spread
   const int gl = adjoint ? kDataOwn : kRadonOwn;        // list gathered at
-  const int t0 = adjoint ? 5 : 0;                       // profile slots
+  const int t0 = adjoint ? 6 : 0;                       // profile slots
   {
     StageTimer t(p, st, t0);
     k_absmax<<<kAbsMaxBlocks, 256, 0, st>>>(in, static_cast<int64_t>(n_in), p->absmax);
+  }
+  {
+    StageTimer t(p, st, t0 + 1);
     if (adjoint)
       k_spread<1><<<p->nchunks[sl], kNtBand, sb, st>>>(p->dg, in, p->absmax, p->ent[sl],
                                                        p->chunk_off[sl], p->chunk_band[sl], p->Hp);
@@ -494,7 +497,7 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
                                                        p->chunk_off[sl], p->chunk_band[sl], p->Hp);
   }
   {
-    StageTimer t(p, st, t0 + 1);
+    StageTimer t(p, st, t0 + 2);
     if (adjoint)
       k_rowfft<1><<<bands, kNtBand, rb, st>>>(p->dg, p->ft, p->tw_t, p->absmax, p->Hp,
                                               p->band_chunk[sl], p->S);
@@ -503,18 +506,18 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
                                               p->band_chunk[sl], p->S);
   }
   {
-    StageTimer t(p, st, t0 + 2);
+    StageTimer t(p, st, t0 + 3);
     if (adjoint)
       k_colfft<true><<<cols, kNtCol, cb, st>>>(p->dg, p->fr, p->tw_r, p->S, p->K);
     else
       k_colfft<false><<<cols, kNtCol, cb, st>>>(p->dg, p->fr, p->tw_r, p->S, p->K);
   }
   {
-    StageTimer t(p, st, t0 + 3);
+    StageTimer t(p, st, t0 + 4);
     k_rowifft<<<bands, kNtBand, rb, st>>>(p->dg, p->ft, p->tw_t, p->S, p->Cr);
   }
   {
-    StageTimer t(p, st, t0 + 4);
+    StageTimer t(p, st, t0 + 5);
     if (adjoint)
       k_gather<1><<<p->nchunks[gl], kNtBand, gb, st>>>(p->dg, p->Cr, p->ent[gl], p->chunk_off[gl],
                                                        p->chunk_band[gl], p->nchunks[gl], out);

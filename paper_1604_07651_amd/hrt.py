@@ -94,8 +94,9 @@ class Plan:
                           self.data_shape, stream, "hrt_direct_adjoint")
 
     # kernels in the order of the library's profile slots
-    STAGES = ("fwd_spread", "fwd_rowfft", "fwd_colfft", "fwd_rowifft", "fwd_gather",
-              "adj_spread", "adj_rowfft", "adj_colfft", "adj_rowifft", "adj_gather")
+    STAGES = ("fwd_absmax", "fwd_spread", "fwd_rowfft", "fwd_colfft", "fwd_rowifft",
+              "fwd_gather", "adj_absmax", "adj_spread", "adj_rowfft", "adj_colfft",
+              "adj_rowifft", "adj_gather")
 
     def profile_begin(self, max_records: int) -> None:
         """Start per-kernel HIP-event timing of forward/adjoint launches."""

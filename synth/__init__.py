@@ -7,8 +7,8 @@ code of the method.
 """
 from .gathers import (GridDesc, CONFIGS, config_desc, ricker, ricker_gather,
                       config_gather, gaussian_sy_gather, trace_mask,
-                      batch_descs, batch_gathers, random_pair)
+                      batch_descs, batch_gathers, random_pair, c5_batch)
 
 __all__ = ["GridDesc", "CONFIGS", "config_desc", "ricker", "ricker_gather",
            "config_gather", "gaussian_sy_gather", "trace_mask", "batch_descs",
-           "batch_gathers", "random_pair"]
+           "batch_gathers", "random_pair", "c5_batch"]

@@ -137,6 +137,21 @@ def trace_mask(nx: int, frac_missing: float, seed: int) -> np.ndarray:
     return m
 
 
+def c5_batch(n: int = 16, frac_missing: float = 0.5):
+    """Trace-interpolation workload: n gathers of C2 shape and physics
+    (1024 x 512, x in [0, 4] km, 30 events, 25 Hz) without noise, gather b
+    drawn with seed 500 + b, and for each a mask over offsets with
+    round(frac * 512) traces missing (its own generator, seed 500 + b).
+    Returns (desc, [f_b (nx, nt)], [keep_b (nx,) bool])."""
+    c = CONFIGS["c2"]
+    desc = c["desc"]
+    fs, keeps = [], []
+    for b in range(n):
+        fs.append(ricker_gather(desc, c["events"], c["freq"], 500 + b, c["tau"]))
+        keeps.append(trace_mask(desc.nx, frac_missing, 500 + b))
+    return desc, fs, keeps
+
+
 def batch_descs(n: int = 64, seed: int = 4):
     """Uneven batch: nt in {512, 1024, 2048}, nx in {128, ..., 1024} step 128,
     ntau = nt, nq = nx, dt = 2 ms, dx = 4/1023 km."""
