@@ -159,6 +159,19 @@ void hrt_graph_destroy(hrt_graph_t graph);
 hrt_status hrt_opnorm2(hrt_plan_t plan, int32_t iters, uint64_t seed, float* work_data,
                        float* work_data2, float* work_radon, double* out, void* stream);
 
+/* Multiple attenuation in the Radon domain (Section 6): given the gather f
+ * float32[nx][nt] and a (sparse) Radon panel g float32[nq][ntau] of it, for
+ * instance from hrt_ista_iterate, keep the multiples' part of the panel,
+ * the samples with q_l > qb0 + qb_slope * tau_i (slower moveout than the
+ * border line; the decision in float64, q_l = q0 + l dq, tau_i = tau0 +
+ * i dtau), take it back to the gather with the adjoint, and subtract:
+ *   out = f - R_h^T (g restricted to the multiples' side).
+ * out float32[nx][nt] receives the primaries; work_radon float32[nq][ntau]
+ * is caller-owned scratch.  Enqueues only; arrays must not overlap (f and g
+ * may be read-only). */
+hrt_status hrt_demultiple(hrt_plan_t plan, const float* f, const float* g, double qb0,
+                          double qb_slope, float* out, float* work_radon, void* stream);
+
 /* Copy of the plan's summary. */
 hrt_status hrt_query(hrt_plan_t plan, hrt_info* out);
 

@@ -18,8 +18,9 @@ convolutions in log-polar coordinates"):
 
 Supporting modules: `geometry` (rescaling, sector placement, coordinate maps,
 lattice sizing), `bspline` (cubic cardinal B-spline), `kernel` (the spectrum of
-zeta by quadrature), `ista` (soft-thresholding iterations of Section 3).
+zeta by quadrature), `ista` (soft-thresholding iterations of Section 3),
+`demultiple` (Radon-domain multiple attenuation of Section 6).
 All arithmetic is float64.  Readings of points where the paper is silent or
 garbled are stated in each function's docstring.
 """
-from . import bspline, geometry, kernel, logpolar, direct, ista  # noqa: F401
+from . import bspline, geometry, kernel, logpolar, direct, ista, demultiple  # noqa: F401

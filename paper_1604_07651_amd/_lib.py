@@ -58,6 +58,8 @@ SIGNATURES = [
     ("hrt_graph_destroy", None, [C.c_void_p]),
     ("hrt_opnorm2", C.c_int, [C.c_void_p, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    ("hrt_demultiple", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                 C.c_void_p, C.c_void_p, C.c_void_p]),
     ("hrt_plan_destroy", None, [C.c_void_p]),
     ("hrt_status_string", C.c_char_p, [C.c_int]),
     ("hrt_last_error", C.c_char_p, []),

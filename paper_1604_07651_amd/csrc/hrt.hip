@@ -697,6 +697,29 @@ hrt_status hrt_opnorm2(hrt_plan_t p, int32_t iters, uint64_t seed, float* work_d
   return HRT_OK;
 }
 
+hrt_status hrt_demultiple(hrt_plan_t p, const float* f, const float* g, double qb0,
+                          double qb_slope, float* out, float* work_radon, void* stream) {
+  hrt_status s = check_plan(p);
+  if (s != HRT_OK) return s;
+  if (!f || !g || !out || !work_radon) return set_err(HRT_ERR_INVALID_ARG, "null array");
+  const hrt_desc& d = p->g.d;
+  const int64_t n_data = static_cast<int64_t>(d.nx) * d.nt;
+  const int64_t n_radon = static_cast<int64_t>(d.nq) * d.ntau;
+  const size_t nd = n_data * sizeof(float), nr = n_radon * sizeof(float);
+  if (overlaps(out, nd, f, nd) || overlaps(out, nd, g, nr) || overlaps(out, nd, work_radon, nr) ||
+      overlaps(work_radon, nr, g, nr) || overlaps(work_radon, nr, f, nd))
+    return set_err(HRT_ERR_INVALID_ARG, "arrays overlap");
+  DeviceGuard guard(p->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  k_mute_multiples<<<vec_blocks(n_radon), kVecThreads, 0, st>>>(
+      g, work_radon, d.ntau, d.nq, d.tau0, d.dtau, d.q0, d.dq, qb0, qb_slope);
+  if ((s = launch_chain(p, work_radon, out, stream, true)) != HRT_OK) return s;
+  k_residual<<<vec_blocks(n_data), kVecThreads, 0, st>>>(f, nullptr, out, n_data);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(e, "demultiple launch");
+  return HRT_OK;
+}
+
 hrt_status hrt_direct_forward(hrt_plan_t p, const float* f, float* g, void* stream) {
   hrt_status s = check_plan(p);
   if (s != HRT_OK) return s;

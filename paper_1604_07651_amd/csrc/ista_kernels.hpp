@@ -1,6 +1,7 @@
 // Element-wise kernels of the soft-thresholding iteration (Section 3, eqs.
-// iters and itersmd) and the float64 reductions of the power iteration that
-// bounds its step size.
+// iters and itersmd), the float64 reductions of the power iteration that
+// bounds its step size, and the Radon-domain mute of multiple attenuation
+// (Section 6).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -71,6 +72,26 @@ __global__ __launch_bounds__(kVecThreads) void k_scale(float* __restrict__ x,
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += stride)
     x[i] = sf * y[i];
+}
+
+// Multiple attenuation (Section 6): keep the part of a Radon panel on the
+// multiples' side of a border line in the (tau, q) plane, out[l][i] = g[l][i]
+// where q_l > qb0 + qb_slope * tau_i, else 0.  The border decision is taken
+// in float64 without contraction: q_l = q0 + l dq, tau_i = tau0 + i dtau.
+__global__ __launch_bounds__(kVecThreads) void k_mute_multiples(
+    const float* __restrict__ g, float* __restrict__ out, int ntau, int nq, double tau0,
+    double dtau, double q0, double dq, double qb0, double qb_slope) {
+  const int64_t n = static_cast<int64_t>(ntau) * nq;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < n;
+       idx += stride) {
+    const int l = static_cast<int>(idx / ntau);
+    const int i = static_cast<int>(idx - static_cast<int64_t>(l) * ntau);
+    const double q = __dadd_rn(q0, __dmul_rn(static_cast<double>(l), dq));
+    const double tau = __dadd_rn(tau0, __dmul_rn(static_cast<double>(i), dtau));
+    const double qb = __dadd_rn(qb0, __dmul_rn(qb_slope, tau));
+    out[idx] = q > qb ? g[idx] : 0.0f;
+  }
 }
 
 }  // namespace hrt

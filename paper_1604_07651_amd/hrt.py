@@ -174,6 +174,24 @@ class Plan:
         return out.value
 
 
+    def demultiple(self, f, g, qb0: float, qb_slope: float = 0.0, out=None, work=None,
+                   stream=None) -> torch.Tensor:
+        """Primaries f - R^T (g where q > qb0 + qb_slope tau) (Section 6)."""
+        self._check_in(f, self.data_shape, "f")
+        self._check_in(g, self.radon_shape, "g")
+        if out is None:
+            out = torch.empty(self.data_shape, device=self.device)
+        self._check_in(out, self.data_shape, "out")
+        wr = torch.empty(self.radon_shape, device=self.device) if work is None else work
+        self._check_in(wr, self.radon_shape, "work")
+        _lib.check(self._lib.hrt_demultiple(self._h, C.c_void_p(f.data_ptr()),
+                                            C.c_void_p(g.data_ptr()), float(qb0),
+                                            float(qb_slope), C.c_void_p(out.data_ptr()),
+                                            C.c_void_p(wr.data_ptr()), _stream_handle(stream)),
+                   "hrt_demultiple")
+        return out
+
+
 class IstaGraph:
     """An executable HIP graph of soft-thresholding iterations (keeps the
     arrays it was captured on alive)."""

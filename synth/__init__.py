@@ -7,8 +7,9 @@ code of the method.
 """
 from .gathers import (GridDesc, CONFIGS, config_desc, ricker, ricker_gather,
                       config_gather, gaussian_sy_gather, trace_mask,
-                      batch_descs, batch_gathers, random_pair, c5_batch)
+                      batch_descs, batch_gathers, random_pair, c5_batch,
+                      demultiple_gather)
 
 __all__ = ["GridDesc", "CONFIGS", "config_desc", "ricker", "ricker_gather",
            "config_gather", "gaussian_sy_gather", "trace_mask", "batch_descs",
-           "batch_gathers", "random_pair", "c5_batch"]
+           "batch_gathers", "random_pair", "c5_batch", "demultiple_gather"]

@@ -152,6 +152,17 @@ def c5_batch(n: int = 16, frac_missing: float = 0.5):
     return desc, fs, keeps
 
 
+def demultiple_gather(desc: GridDesc, seed: int, primaries: int = 6, multiples: int = 4,
+                      freq: float = 25.0, v_prim=(2.2, 4.0), v_mult=(1.5, 1.9)):
+    """Primaries (velocities v_prim) plus slower multiples (v_mult, arriving in
+    the later 60 % of the record), Ricker events.  Returns (total, primaries,
+    multiples), each (nx, nt); with the default velocities every multiple
+    has q > 1/1.9 s/km and every primary q < 1/2.2 s/km."""
+    prim = ricker_gather(desc, primaries, freq, seed, ("rel", 0.1, 0.9), vel=v_prim)
+    mult = ricker_gather(desc, multiples, freq, seed + 1, ("rel", 0.3, 0.9), vel=v_mult)
+    return prim + mult, prim, mult
+
+
 def batch_descs(n: int = 64, seed: int = 4):
     """Uneven batch: nt in {512, 1024, 2048}, nx in {128, ..., 1024} step 128,
     ntau = nt, nq = nx, dt = 2 ms, dx = 4/1023 km."""
