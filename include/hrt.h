@@ -172,6 +172,27 @@ hrt_status hrt_opnorm2(hrt_plan_t plan, int32_t iters, uint64_t seed, float* wor
 hrt_status hrt_demultiple(hrt_plan_t plan, const float* f, const float* g, double qb0,
                           double qb_slope, float* out, float* work_radon, void* stream);
 
+/* Uneven batches: n gathers of different grids transformed by one launch
+ * per kernel for the whole batch (every kernel's work items cover all
+ * gathers, largest gathers first), so that small gathers fill the GPU
+ * together.  hrt_batch_create builds one plan per description (as
+ * hrt_plan_create) and the batch tables; the batch owns its plans.  Arrays
+ * are packed: gather i's data f_i[nx_i][nt_i] starts at f + data_off[i] and
+ * its Radon panel at g + radon_off[i] (offsets in floats, from
+ * hrt_batch_offsets, n + 1 entries each, the last being the total).  The
+ * batch calls enqueue only; the member plans' workspaces are shared with
+ * them, so a batch and its plans must not run concurrently. */
+typedef struct hrt_batch_s* hrt_batch_t;
+hrt_status hrt_batch_create(const hrt_desc* descs, int32_t n, hrt_batch_t* out);
+hrt_status hrt_batch_offsets(hrt_batch_t batch, int64_t* data_off, int64_t* radon_off);
+hrt_status hrt_batch_forward(hrt_batch_t batch, const float* f_packed, float* g_packed,
+                             void* stream);
+hrt_status hrt_batch_adjoint(hrt_batch_t batch, const float* g_packed, float* f_packed,
+                             void* stream);
+/* The plan of gather i (owned by the batch; do not destroy it). */
+hrt_status hrt_batch_plan(hrt_batch_t batch, int32_t i, hrt_plan_t* out);
+void hrt_batch_destroy(hrt_batch_t batch);
+
 /* Copy of the plan's summary. */
 hrt_status hrt_query(hrt_plan_t plan, hrt_info* out);
 

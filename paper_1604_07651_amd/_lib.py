@@ -60,6 +60,12 @@ SIGNATURES = [
                               C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     ("hrt_demultiple", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                  C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hrt_batch_create", C.c_int, [C.POINTER(HrtDesc), C.c_int32, C.POINTER(C.c_void_p)]),
+    ("hrt_batch_offsets", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("hrt_batch_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hrt_batch_adjoint", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hrt_batch_plan", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    ("hrt_batch_destroy", None, [C.c_void_p]),
     ("hrt_plan_destroy", None, [C.c_void_p]),
     ("hrt_status_string", C.c_char_p, [C.c_int]),
     ("hrt_last_error", C.c_char_p, []),

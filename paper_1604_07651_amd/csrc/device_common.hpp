@@ -13,11 +13,24 @@ namespace hrt {
 
 constexpr int kNtBand = kBandThreads;  // threads of the band kernels
 constexpr int kNtCol = kColThreads;    // threads of the column kernel
-constexpr int kAbsMaxBlocks = 1024;  // partial maxima of the input
+constexpr int kAbsMaxBlocks = 1024;    // partial maxima of the input, one gather
+constexpr int kAbsMaxBlocksBatch = 64; // ... per gather of a batch
 
-// Everything the lattice kernels need about one plan (passed by value).
+// The four point lists of a plan, cut into chunks (see BandLists).
+enum { kDataSpread = 0, kDataOwn = 1, kRadonSpread = 2, kRadonOwn = 3 };
+struct DevList {
+  const uint4* ent;
+  const int64_t* chunk_off;
+  const int* chunk_band;
+  const int* band_chunk;
+  int nchunks;
+};
+
+// Everything the kernels need about one gather's plan.  The kernels read it
+// from a device table, one entry per gather of a batch (one for a single
+// plan), and get their work as (gather, item) pairs.
 struct DevGeo {
-  int nt, nx;
+  int nt, nx, ntau, nq;
   int Mt, Mr, K1, K2, u0, u1, R, nbands;
   int xw0, W;         // angle columns [xw0, xw0 + W) that points can touch
   int x_frac_bits;    // fraction bits of the angle coordinate of a point entry
@@ -27,7 +40,18 @@ struct DevGeo {
   int col_inplace, col_batch;
   float knorm;                  // 1/(Mt Mr): both inverse FFTs are unnormalised
   float cmax_data, cmax_radon;  // bounds of the accumulated cells per unit input
+  int absmax_blocks;            // partial maxima of this gather's input
+  int64_t data_off, radon_off;  // this gather's offsets in packed batch arrays
+  FftDev ft, fr;                // angle and log-radius FFTs
+  const float2* tw_t;
+  const float2* tw_r;
+  const float2* K;              // kernel multiplier [K1][K2]
+  float2* S;                    // half spectrum [K1][Mr]
+  int* Hp;                      // spread partial rows [chunk][R][W]
+  float* Cr;                    // real rows after the inverse row FFT [u1-u0][W]
+  float* absmax;                // absmax_blocks partial maxima
   const int* jmin;              // first kept time sample of each trace
+  DevList lists[4];
 };
 
 // Cubic B-spline weights of taps i0-1 .. i0+2 for fractional offset f.

@@ -31,11 +31,21 @@
 namespace hrt {
 constexpr uint64_t kMagic = 0x6872745f706c616eull;
 constexpr uint64_t kGraphMagic = 0x6872745f67726170ull;
+constexpr uint64_t kBatchMagic = 0x6872745f62617463ull;
 static_assert(kTwLds * sizeof(float2) + kNtBand / 64 * sizeof(float) <= kBandStaticLds,
               "static LDS");
 static_assert(sizeof(PointEntry) == sizeof(uint4), "point entry layout");
-// band lists: data spread, data owned, Radon spread, Radon owned
-enum { kDataSpread = 0, kDataOwn = 1, kRadonSpread = 2, kRadonOwn = 3 };
+// work-item lists of a plan's launches
+enum {
+  kItAbsmax = 0,       // partial maxima
+  kItSpreadData = 1,   // chunks of the data spread list
+  kItSpreadRadon = 2,  // chunks of the Radon spread list
+  kItBands = 3,        // bands (row FFTs)
+  kItCols = 4,         // column groups (column pass)
+  kItGatherRadon = 5,  // chunks of the Radon owned list (forward gather)
+  kItGatherData = 6,   // chunks of the data owned list (adjoint gather)
+  kItemSets = 7
+};
 }  // namespace hrt
 
 // ==================================================================== ABI ==
@@ -65,6 +75,9 @@ struct hrt_plan_s {
   float* Cr = nullptr;      // real lattice rows after the inverse row FFT
   float* absmax = nullptr;  // kAbsMaxBlocks partial maxima of the current input
   double* dot = nullptr;    // kDotBlocks partial sums of the power iteration
+  DevGeo* geo_dev = nullptr;         // the plan's descriptor, on the device
+  int2* items[kItemSets] = {};       // work items (gather 0, index)
+  int nitems[kItemSets] = {};
   // per-kernel timing (hrt_profile_begin / hrt_profile_end)
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_stage;
@@ -133,8 +146,11 @@ hrt_status upload(T* dst, const std::vector<T>& src) {
 }
 
 void free_plan(hrt_plan_s* p) {
-  void* ptrs[] = {p->S, p->K, p->tw_t, p->tw_r, p->jmin, p->absmax, p->Hp, p->Cr, p->dot};
+  void* ptrs[] = {p->S, p->K, p->tw_t, p->tw_r, p->jmin, p->absmax, p->Hp, p->Cr, p->dot,
+                  p->geo_dev};
   for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  for (int2* q : p->items)
     if (q) (void)hipFree(q);
   for (int i = 0; i < 4; ++i) {
     void* lists[] = {p->ent[i], p->chunk_off[i], p->chunk_band[i], p->band_chunk[i]};
@@ -363,18 +379,29 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
     // (the device limit less its static LDS), whatever this plan needs
     std::lock_guard<std::mutex> lk(g_attr_mu);
     const int64_t cap = std::min<int64_t>(lds_max, 163840);
-    const void* fns[] = {reinterpret_cast<const void*>(&k_spread<0>),
-                         reinterpret_cast<const void*>(&k_spread<1>),
-                         reinterpret_cast<const void*>(&k_rowfft<0>),
-                         reinterpret_cast<const void*>(&k_rowfft<1>),
-                         reinterpret_cast<const void*>(&k_colfft<false>),
-                         reinterpret_cast<const void*>(&k_colfft<true>),
-                         reinterpret_cast<const void*>(&k_rowifft),
-                         reinterpret_cast<const void*>(&k_gather<0>),
-                         reinterpret_cast<const void*>(&k_gather<1>)};
+    const void* fns[] = {reinterpret_cast<const void*>(&k_spread<0, false>),
+                         reinterpret_cast<const void*>(&k_spread<1, false>),
+                         reinterpret_cast<const void*>(&k_rowfft<0, false>),
+                         reinterpret_cast<const void*>(&k_rowfft<1, false>),
+                         reinterpret_cast<const void*>(&k_colfft<false, false>),
+                         reinterpret_cast<const void*>(&k_colfft<true, false>),
+                         reinterpret_cast<const void*>(&k_rowifft<false>),
+                         reinterpret_cast<const void*>(&k_gather<0, false>),
+                         reinterpret_cast<const void*>(&k_gather<1, false>),
+                         reinterpret_cast<const void*>(&k_spread<0, true>),
+                         reinterpret_cast<const void*>(&k_spread<1, true>),
+                         reinterpret_cast<const void*>(&k_rowfft<0, true>),
+                         reinterpret_cast<const void*>(&k_rowfft<1, true>),
+                         reinterpret_cast<const void*>(&k_colfft<false, true>),
+                         reinterpret_cast<const void*>(&k_colfft<true, true>),
+                         reinterpret_cast<const void*>(&k_rowifft<true>),
+                         reinterpret_cast<const void*>(&k_gather<0, true>),
+                         reinterpret_cast<const void*>(&k_gather<1, true>)};
     const int need[] = {g.spread_bytes, g.spread_bytes, g.row_bytes, g.row_bytes,
                         g.col_bytes,    g.col_bytes,    g.row_bytes, g.gather_bytes,
-                        g.gather_bytes};
+                        g.gather_bytes, g.spread_bytes, g.spread_bytes, g.row_bytes,
+                        g.row_bytes,    g.col_bytes,    g.col_bytes,    g.row_bytes,
+                        g.gather_bytes, g.gather_bytes};
     constexpr int nfn = sizeof(fns) / sizeof(fns[0]);
     struct {
       const void* fn;
@@ -422,6 +449,43 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
   G.jmin = p->jmin;
   p->ft = to_dev(g.fft_t);
   p->fr = to_dev(g.fft_r);
+  G.ntau = g.d.ntau; G.nq = g.d.nq;
+  G.absmax_blocks = kAbsMaxBlocks;
+  G.data_off = 0; G.radon_off = 0;
+  G.ft = p->ft; G.fr = p->fr;
+  G.tw_t = p->tw_t; G.tw_r = p->tw_r;
+  G.K = p->K; G.S = p->S; G.Hp = p->Hp; G.Cr = p->Cr; G.absmax = p->absmax;
+  for (int i = 0; i < 4; ++i)
+    G.lists[i] = DevList{p->ent[i], p->chunk_off[i], p->chunk_band[i], p->band_chunk[i],
+                         p->nchunks[i]};
+  {
+    // the descriptor and the single-gather work lists on the device
+    std::vector<int2> it[kItemSets];
+    for (int b = 0; b < kAbsMaxBlocks; ++b) it[kItAbsmax].push_back(make_int2(0, b));
+    for (int c = 0; c < p->nchunks[kDataSpread]; ++c) it[kItSpreadData].push_back(make_int2(0, c));
+    for (int c = 0; c < p->nchunks[kRadonSpread]; ++c)
+      it[kItSpreadRadon].push_back(make_int2(0, c));
+    for (int b = 0; b < g.nbands; ++b) it[kItBands].push_back(make_int2(0, b));
+    for (int c = 0; c < (g.K1 + g.col_batch - 1) / g.col_batch; ++c)
+      it[kItCols].push_back(make_int2(0, c));
+    for (int c = 0; c < p->nchunks[kRadonOwn]; ++c) it[kItGatherRadon].push_back(make_int2(0, c));
+    for (int c = 0; c < p->nchunks[kDataOwn]; ++c) it[kItGatherData].push_back(make_int2(0, c));
+    std::vector<DevGeo> one(1, G);
+    if ((s = dev_alloc(&p->geo_dev, 1, total)) || (s = upload(p->geo_dev, one))) {
+      free_plan(p);
+      delete p;
+      return s;
+    }
+    for (int k = 0; k < kItemSets; ++k) {
+      p->nitems[k] = static_cast<int>(it[k].size());
+      if ((s = dev_alloc(&p->items[k], std::max<size_t>(1, it[k].size()), total)) ||
+          (s = upload(p->items[k], it[k]))) {
+        free_plan(p);
+        delete p;
+        return s;
+      }
+    }
+  }
 
   DirectGeo& D = p->dd;
   D.nt = g.d.nt; D.nx = g.d.nx; D.ntau = g.d.ntau; D.nq = g.d.nq;
@@ -477,53 +541,36 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
   (void)hipGetLastError();  // do not report an earlier, unrelated error
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const Geometry& g = p->g;
-  const dim3 bands(g.nbands);
-  const dim3 cols((g.K1 + g.col_batch - 1) / g.col_batch);
   const size_t sb = g.spread_bytes, rb = g.row_bytes, cb = g.col_bytes, gb = g.gather_bytes;
-  const int sl = adjoint ? kRadonSpread : kDataSpread;  // list spread
-  const int gl = adjoint ? kDataOwn : kRadonOwn;        // list gathered at
-  const int t0 = adjoint ? 6 : 0;                       // profile slots
-  {
-    StageTimer t(p, st, t0);
-    k_absmax<<<kAbsMaxBlocks, 256, 0, st>>>(in, static_cast<int64_t>(n_in), p->absmax);
-  }
-  {
-    StageTimer t(p, st, t0 + 1);
-    if (adjoint)
-      k_spread<1><<<p->nchunks[sl], kNtBand, sb, st>>>(p->dg, in, p->absmax, p->ent[sl],
-                                                       p->chunk_off[sl], p->chunk_band[sl], p->Hp);
-    else
-      k_spread<0><<<p->nchunks[sl], kNtBand, sb, st>>>(p->dg, in, p->absmax, p->ent[sl],
-                                                       p->chunk_off[sl], p->chunk_band[sl], p->Hp);
-  }
-  {
-    StageTimer t(p, st, t0 + 2);
-    if (adjoint)
-      k_rowfft<1><<<bands, kNtBand, rb, st>>>(p->dg, p->ft, p->tw_t, p->absmax, p->Hp,
-                                              p->band_chunk[sl], p->S);
-    else
-      k_rowfft<0><<<bands, kNtBand, rb, st>>>(p->dg, p->ft, p->tw_t, p->absmax, p->Hp,
-                                              p->band_chunk[sl], p->S);
-  }
-  {
-    StageTimer t(p, st, t0 + 3);
-    if (adjoint)
-      k_colfft<true><<<cols, kNtCol, cb, st>>>(p->dg, p->fr, p->tw_r, p->S, p->K);
-    else
-      k_colfft<false><<<cols, kNtCol, cb, st>>>(p->dg, p->fr, p->tw_r, p->S, p->K);
-  }
-  {
-    StageTimer t(p, st, t0 + 4);
-    k_rowifft<<<bands, kNtBand, rb, st>>>(p->dg, p->ft, p->tw_t, p->S, p->Cr);
-  }
-  {
-    StageTimer t(p, st, t0 + 5);
-    if (adjoint)
-      k_gather<1><<<p->nchunks[gl], kNtBand, gb, st>>>(p->dg, p->Cr, p->ent[gl], p->chunk_off[gl],
-                                                       p->chunk_band[gl], p->nchunks[gl], out);
-    else
-      k_gather<0><<<p->nchunks[gl], kNtBand, gb, st>>>(p->dg, p->Cr, p->ent[gl], p->chunk_off[gl],
-                                                       p->chunk_band[gl], p->nchunks[gl], out);
+  const DevGeo& G = p->dg;
+  const int* ni = p->nitems;
+  const int t0 = adjoint ? 6 : 0;  // profile slots
+  if (!adjoint) {
+    { StageTimer t(p, st, t0);
+      k_absmax<0, false><<<ni[kItAbsmax], 256, 0, st>>>(G, nullptr, nullptr, in); }
+    { StageTimer t(p, st, t0 + 1);
+      k_spread<0, false><<<ni[kItSpreadData], kNtBand, sb, st>>>(G, nullptr, nullptr, in); }
+    { StageTimer t(p, st, t0 + 2);
+      k_rowfft<0, false><<<ni[kItBands], kNtBand, rb, st>>>(G, nullptr, nullptr); }
+    { StageTimer t(p, st, t0 + 3);
+      k_colfft<false, false><<<ni[kItCols], kNtCol, cb, st>>>(G, nullptr, nullptr); }
+    { StageTimer t(p, st, t0 + 4);
+      k_rowifft<false><<<ni[kItBands], kNtBand, rb, st>>>(G, nullptr, nullptr); }
+    { StageTimer t(p, st, t0 + 5);
+      k_gather<0, false><<<ni[kItGatherRadon], kNtBand, gb, st>>>(G, nullptr, nullptr, out); }
+  } else {
+    { StageTimer t(p, st, t0);
+      k_absmax<1, false><<<ni[kItAbsmax], 256, 0, st>>>(G, nullptr, nullptr, in); }
+    { StageTimer t(p, st, t0 + 1);
+      k_spread<1, false><<<ni[kItSpreadRadon], kNtBand, sb, st>>>(G, nullptr, nullptr, in); }
+    { StageTimer t(p, st, t0 + 2);
+      k_rowfft<1, false><<<ni[kItBands], kNtBand, rb, st>>>(G, nullptr, nullptr); }
+    { StageTimer t(p, st, t0 + 3);
+      k_colfft<true, false><<<ni[kItCols], kNtCol, cb, st>>>(G, nullptr, nullptr); }
+    { StageTimer t(p, st, t0 + 4);
+      k_rowifft<false><<<ni[kItBands], kNtBand, rb, st>>>(G, nullptr, nullptr); }
+    { StageTimer t(p, st, t0 + 5);
+      k_gather<1, false><<<ni[kItGatherData], kNtBand, gb, st>>>(G, nullptr, nullptr, out); }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, adjoint ? "adjoint launch" : "forward launch");
@@ -744,6 +791,179 @@ hrt_status hrt_direct_adjoint(hrt_plan_t p, const float* g, float* f, void* stre
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, "direct adjoint launch");
   return HRT_OK;
+}
+
+// ------------------------------------------------------------ batches --
+
+struct hrt_batch_s {
+  uint64_t magic;
+  int device;
+  std::vector<hrt_plan_t> plans;
+  std::vector<int64_t> data_off, radon_off;  // n + 1 each, in floats
+  DevGeo* geos = nullptr;                    // one descriptor per gather
+  int2* items[kItemSets] = {};
+  int nitems[kItemSets] = {};
+  int spread_bytes = 0, row_bytes = 0, col_bytes = 0, gather_bytes = 0;
+};
+
+namespace {
+void free_batch(hrt_batch_s* b) {
+  if (b->geos) (void)hipFree(b->geos);
+  for (int2* q : b->items)
+    if (q) (void)hipFree(q);
+  for (hrt_plan_t q : b->plans) hrt_plan_destroy(q);
+  b->magic = 0;
+  delete b;
+}
+
+hrt_status check_batch(hrt_batch_t b) {
+  if (!b || b->magic != kBatchMagic) return set_err(HRT_ERR_BAD_HANDLE, "bad batch handle");
+  return HRT_OK;
+}
+}  // namespace
+
+hrt_status hrt_batch_create(const hrt_desc* descs, int32_t n, hrt_batch_t* out) {
+  if (!descs || !out || n < 1) return set_err(HRT_ERR_INVALID_ARG, "null argument or n < 1");
+  *out = nullptr;
+  auto* b = new hrt_batch_s();
+  b->magic = kBatchMagic;
+  HRT_HIP(hipGetDevice(&b->device), "hipGetDevice");
+  b->data_off.assign(n + 1, 0);
+  b->radon_off.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    hrt_plan_t pl = nullptr;
+    hrt_status s = hrt_plan_create(&descs[i], &pl);
+    if (s != HRT_OK) {
+      const std::string e = g_last_error;
+      free_batch(b);
+      return set_err(s, "gather " + std::to_string(i) + ": " + e);
+    }
+    b->plans.push_back(pl);
+    const Geometry& g = pl->g;
+    b->data_off[i + 1] = b->data_off[i] + static_cast<int64_t>(g.d.nx) * g.d.nt;
+    b->radon_off[i + 1] = b->radon_off[i] + static_cast<int64_t>(g.d.nq) * g.d.ntau;
+    b->spread_bytes = std::max(b->spread_bytes, g.spread_bytes);
+    b->row_bytes = std::max(b->row_bytes, g.row_bytes);
+    b->col_bytes = std::max(b->col_bytes, g.col_bytes);
+    b->gather_bytes = std::max(b->gather_bytes, g.gather_bytes);
+  }
+  // descriptors with the packed offsets; work items, largest gathers first so
+  // that the small ones fill in at the end of each launch
+  std::vector<DevGeo> geos(n);
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) {
+    geos[i] = b->plans[i]->dg;
+    geos[i].data_off = b->data_off[i];
+    geos[i].radon_off = b->radon_off[i];
+    geos[i].absmax_blocks = kAbsMaxBlocksBatch;
+    order[i] = i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return b->data_off[x + 1] - b->data_off[x] > b->data_off[y + 1] - b->data_off[y];
+  });
+  std::vector<int2> it[kItemSets];
+  for (int i : order) {
+    const hrt_plan_s* pl = b->plans[i];
+    for (int k = 0; k < kAbsMaxBlocksBatch; ++k) it[kItAbsmax].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->nchunks[kDataSpread]; ++k) it[kItSpreadData].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->nchunks[kRadonSpread]; ++k)
+      it[kItSpreadRadon].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->g.nbands; ++k) it[kItBands].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->nitems[kItCols]; ++k) it[kItCols].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->nchunks[kRadonOwn]; ++k) it[kItGatherRadon].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->nchunks[kDataOwn]; ++k) it[kItGatherData].push_back(make_int2(i, k));
+  }
+  DeviceGuard guard(b->device);
+  size_t total = 0;
+  hrt_status s = HRT_OK;
+  if ((s = dev_alloc(&b->geos, n, total)) || (s = upload(b->geos, geos))) {
+    free_batch(b);
+    return s;
+  }
+  for (int k = 0; k < kItemSets; ++k) {
+    b->nitems[k] = static_cast<int>(it[k].size());
+    if ((s = dev_alloc(&b->items[k], std::max<size_t>(1, it[k].size()), total)) ||
+        (s = upload(b->items[k], it[k]))) {
+      free_batch(b);
+      return s;
+    }
+  }
+  *out = b;
+  return HRT_OK;
+}
+
+hrt_status hrt_batch_offsets(hrt_batch_t b, int64_t* data_off, int64_t* radon_off) {
+  hrt_status s = check_batch(b);
+  if (s != HRT_OK) return s;
+  for (size_t i = 0; i < b->data_off.size(); ++i) {
+    if (data_off) data_off[i] = b->data_off[i];
+    if (radon_off) radon_off[i] = b->radon_off[i];
+  }
+  return HRT_OK;
+}
+
+hrt_status hrt_batch_plan(hrt_batch_t b, int32_t i, hrt_plan_t* out) {
+  hrt_status s = check_batch(b);
+  if (s != HRT_OK) return s;
+  if (!out || i < 0 || i >= static_cast<int32_t>(b->plans.size()))
+    return set_err(HRT_ERR_INVALID_ARG, "gather index out of range");
+  *out = b->plans[i];
+  return HRT_OK;
+}
+
+static hrt_status batch_chain(hrt_batch_t b, const float* in, float* out, void* stream,
+                              bool adjoint) {
+  hrt_status s = check_batch(b);
+  if (s != HRT_OK) return s;
+  if (!in || !out) return set_err(HRT_ERR_INVALID_ARG, "null array");
+  const size_t nd = static_cast<size_t>(b->data_off.back()) * sizeof(float);
+  const size_t nr = static_cast<size_t>(b->radon_off.back()) * sizeof(float);
+  if (overlaps(in, adjoint ? nr : nd, out, adjoint ? nd : nr))
+    return set_err(HRT_ERR_INVALID_ARG, "input and output overlap");
+  DeviceGuard guard(b->device);
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const DevGeo none{};
+  const DevGeo* geo = b->geos;
+  int2* const* it = b->items;
+  const int* ni = b->nitems;
+  const size_t sb = b->spread_bytes, rb = b->row_bytes, cb = b->col_bytes, gb = b->gather_bytes;
+  if (!adjoint) {
+    k_absmax<0, true><<<ni[kItAbsmax], 256, 0, st>>>(none, geo, it[kItAbsmax], in);
+    k_spread<0, true><<<ni[kItSpreadData], kNtBand, sb, st>>>(none, geo, it[kItSpreadData], in);
+    k_rowfft<0, true><<<ni[kItBands], kNtBand, rb, st>>>(none, geo, it[kItBands]);
+    k_colfft<false, true><<<ni[kItCols], kNtCol, cb, st>>>(none, geo, it[kItCols]);
+    k_rowifft<true><<<ni[kItBands], kNtBand, rb, st>>>(none, geo, it[kItBands]);
+    k_gather<0, true><<<ni[kItGatherRadon], kNtBand, gb, st>>>(none, geo, it[kItGatherRadon],
+                                                               out);
+  } else {
+    k_absmax<1, true><<<ni[kItAbsmax], 256, 0, st>>>(none, geo, it[kItAbsmax], in);
+    k_spread<1, true><<<ni[kItSpreadRadon], kNtBand, sb, st>>>(none, geo, it[kItSpreadRadon],
+                                                               in);
+    k_rowfft<1, true><<<ni[kItBands], kNtBand, rb, st>>>(none, geo, it[kItBands]);
+    k_colfft<true, true><<<ni[kItCols], kNtCol, cb, st>>>(none, geo, it[kItCols]);
+    k_rowifft<true><<<ni[kItBands], kNtBand, rb, st>>>(none, geo, it[kItBands]);
+    k_gather<1, true><<<ni[kItGatherData], kNtBand, gb, st>>>(none, geo, it[kItGatherData],
+                                                              out);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(e, adjoint ? "batch adjoint launch" : "batch forward launch");
+  return HRT_OK;
+}
+
+hrt_status hrt_batch_forward(hrt_batch_t b, const float* f, float* g, void* stream) {
+  return batch_chain(b, f, g, stream, false);
+}
+
+hrt_status hrt_batch_adjoint(hrt_batch_t b, const float* g, float* f, void* stream) {
+  return batch_chain(b, g, f, stream, true);
+}
+
+void hrt_batch_destroy(hrt_batch_t b) {
+  if (!b || b->magic != kBatchMagic) return;
+  DeviceGuard guard(b->device);
+  (void)hipDeviceSynchronize();
+  free_batch(b);
 }
 
 hrt_status hrt_query(hrt_plan_t p, hrt_info* out) {

@@ -3,6 +3,10 @@
 // [u0, u1) are cut into bands of R rows; the point lists of the plan are cut
 // into chunks of at most a fixed number of entries, so that the point
 // kernels get equal work whatever the density of points along the lattice.
+// A single plan passes its gather descriptor by value and workgroup w does
+// item w; a batch (BATCH = true) passes a device table of descriptors and a
+// list of work items (gather, index), workgroup w doing item w, so that one
+// launch covers every gather of the batch.
 //
 //   k_absmax   largest |input| (fixes the spread's fixed-point scale)
 //   k_spread   one workgroup per chunk of a band's spread list: smear the
@@ -29,16 +33,37 @@
 
 namespace hrt {
 
-// Largest |x| over n floats as kAbsMaxBlocks partial maxima (no atomics and
-// nothing to clear, so replays are safe); a non-finite input makes its block
-// report +inf.  16-byte loads when x is 16-byte aligned.
-__global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ x, int64_t n,
-                                                float* __restrict__ partial) {
+// The gather descriptor and the index of this workgroup's work item.
+struct Work {
+  const DevGeo& G;
+  int i;
+};
+template <bool BATCH>
+__device__ __forceinline__ Work work_item(const DevGeo& one, const DevGeo* __restrict__ geos,
+                                          const int2* __restrict__ items) {
+  if (!BATCH) return Work{one, static_cast<int>(blockIdx.x)};
+  const int2 it = items[blockIdx.x];
+  return Work{geos[it.x], it.y};
+}
+
+// Largest |x| of one gather's input (MODE 0: data, MODE 1: Radon) as
+// absmax_blocks partial maxima (no atomics and nothing to clear, so replays
+// are safe); item i is partial i.  A non-finite input makes its block report
+// +inf.  16-byte loads when the gather's array is 16-byte aligned.
+template <int MODE, bool BATCH>
+__global__ __launch_bounds__(256) void k_absmax(DevGeo one, const DevGeo* __restrict__ geos,
+                                                const int2* __restrict__ items,
+                                                const float* __restrict__ in) {
   __shared__ float s_m[4];
+  const Work w = work_item<BATCH>(one, geos, items);
+  const DevGeo& G = w.G;
+  const float* x = in + (MODE == 0 ? G.data_off : G.radon_off);
+  const int64_t n = MODE == 0 ? static_cast<int64_t>(G.nx) * G.nt
+                              : static_cast<int64_t>(G.nq) * G.ntau;
   float m = 0.0f;
   bool bad = false;
-  const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t tid = static_cast<int64_t>(w.i) * blockDim.x + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(G.absmax_blocks) * blockDim.x;
   int64_t done = 0;
   if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
     const float4* x4 = reinterpret_cast<const float4*>(x);
@@ -63,52 +88,54 @@ __global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ x, int
   if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0)
-    partial[blockIdx.x] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
+    G.absmax[w.i] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
 }
 
 // The spread's fixed-point scale: every accumulated cell stays within 2^30
 // (cmax bounds a cell per unit of input); 0 for an all-zero or non-finite
 // input (the latter is reported through `finite`).
-__device__ __forceinline__ float spread_scale(const float* __restrict__ absmax, float cmax,
-                                              float* s_wave, bool& finite) {
+__device__ __forceinline__ float spread_scale(const DevGeo& G, float cmax, float* s_wave,
+                                              bool& finite) {
   float vmax = 0.0f;
-  for (int i = threadIdx.x; i < kAbsMaxBlocks; i += kNtBand) vmax = fmaxf(vmax, absmax[i]);
+  for (int i = threadIdx.x; i < G.absmax_blocks; i += kNtBand) vmax = fmaxf(vmax, G.absmax[i]);
   vmax = block_max(vmax, s_wave);
   finite = vmax <= 3.0e38f;  // false for inf and NaN
   return (vmax > 0.0f && finite) ? 1073741824.0f / (cmax * vmax) : 0.0f;
 }
 
 // Spread of one chunk (MODE 0: data samples of f[nx][nt]; MODE 1: Radon
-// samples of g[nq][ntau]).  Dynamic LDS: the band's R x W fixed-point rows,
-// then a staging buffer for kSpreadStage entries.  The chunk's entries are
-// read coalesced into the staging buffer; thread s then takes a contiguous
-// segment of it, segments dealt lane-major so that the lanes of a wave work
-// far apart on the lattice.
-template <int MODE>
-__global__ __launch_bounds__(kNtBand) void k_spread(
-    DevGeo G, const float* __restrict__ in, const float* __restrict__ absmax,
-    const uint4* __restrict__ ent, const int64_t* __restrict__ chunk_off,
-    const int* __restrict__ chunk_band, int* __restrict__ Hp) {
+// samples of g[nq][ntau]); item i is chunk i of the spread list.  Dynamic
+// LDS: the band's R x W fixed-point rows, then a staging buffer for
+// kSpreadStage entries.  The chunk's entries are read coalesced into the
+// staging buffer; thread s then takes a contiguous segment of it, segments
+// dealt lane-major so that the lanes of a wave work far apart on the lattice.
+template <int MODE, bool BATCH>
+__global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __restrict__ geos,
+                                                    const int2* __restrict__ items,
+                                                    const float* __restrict__ in_base) {
   extern __shared__ int lds_i[];
   __shared__ float s_wave[kNtBand / 64];
-  const int chunk = blockIdx.x;
-  const int band = chunk_band[chunk];
+  const Work w = work_item<BATCH>(one, geos, items);
+  const DevGeo& G = w.G;
+  const DevList& L = G.lists[MODE == 0 ? kDataSpread : kRadonSpread];
+  const float* in = in_base + (MODE == 0 ? G.data_off : G.radon_off);
+  const int chunk = w.i;
+  const int band = L.chunk_band[chunk];
   const int n0 = G.u0 + band * G.R;
   const int nr = min(G.R, G.u1 - n0);
   const int W = G.W;
   int* acc = lds_i;
   uint4* stage = reinterpret_cast<uint4*>(lds_i + G.R * W);
   bool finite;
-  const float scale = spread_scale(absmax, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave,
-                                   finite);
+  const float scale = spread_scale(G, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave, finite);
   for (int i = threadIdx.x; i < nr * W; i += kNtBand) acc[i] = 0;
   __syncthreads();
   if (scale > 0.0f) {
-    const int64_t e0 = chunk_off[chunk], e1 = chunk_off[chunk + 1];
+    const int64_t e0 = L.chunk_off[chunk], e1 = L.chunk_off[chunk + 1];
     const int seg = (threadIdx.x & 63) * (kNtBand / 64) + (threadIdx.x >> 6);
     for (int64_t c0 = e0; c0 < e1; c0 += kSpreadStage) {
       const int n = static_cast<int>(min(static_cast<int64_t>(kSpreadStage), e1 - c0));
-      for (int i = threadIdx.x; i < n; i += kNtBand) stage[i] = ent[c0 + i];
+      for (int i = threadIdx.x; i < n; i += kNtBand) stage[i] = L.ent[c0 + i];
       __syncthreads();
       const int per = (n + kNtBand - 1) / kNtBand;
       int p = seg * per;
@@ -132,33 +159,36 @@ __global__ __launch_bounds__(kNtBand) void k_spread(
     }
   }
   // the chunk's partial rows, R x W (rows past nr unused)
-  int* dst = Hp + static_cast<size_t>(chunk) * G.R * W;
+  int* dst = G.Hp + static_cast<size_t>(chunk) * G.R * W;
   for (int i = threadIdx.x; i < nr * W; i += kNtBand) dst[i] = acc[i];
 }
 
-// Row FFT of one band: the sum of its chunks' partials, fixed point to
-// float (NaN everywhere for a non-finite input), rows (2p, 2p+1) into
-// complex pair p, FFT along the angle, and the k1 < K1 half spectrum of both
-// rows to S.  Dynamic LDS: the pairs, then the FFT scratch (if any).
-template <int MODE>
-__global__ __launch_bounds__(kNtBand, 6) void k_rowfft(
-    DevGeo G, FftDev F, const float2* __restrict__ tw, const float* __restrict__ absmax,
-    const int* __restrict__ Hp, const int* __restrict__ band_chunk, float2* __restrict__ S) {
+// Row FFT of one band (item i = band i): the sum of its chunks' partials,
+// fixed point to float (NaN everywhere for a non-finite input), rows
+// (2p, 2p+1) into complex pair p, FFT along the angle, and the k1 < K1 half
+// spectrum of both rows to S.  Dynamic LDS: the pairs, then the FFT scratch
+// (if any).
+template <int MODE, bool BATCH>
+__global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
+                                                       const DevGeo* __restrict__ geos,
+                                                       const int2* __restrict__ items) {
   extern __shared__ float2 lds[];
   __shared__ float s_wave[kNtBand / 64];
   __shared__ float2 s_tw[kTwLds];
-  const int band = blockIdx.x;
-  load_twiddles<kNtBand>(s_tw, tw, G.Mt);
+  const Work w = work_item<BATCH>(one, geos, items);
+  const DevGeo& G = w.G;
+  const DevList& L = G.lists[MODE == 0 ? kDataSpread : kRadonSpread];
+  const int band = w.i;
+  load_twiddles<kNtBand>(s_tw, G.tw_t, G.Mt);
   const int n0 = G.u0 + band * G.R;
   const int nr = min(G.R, G.u1 - n0);
   const int npair = nr >> 1;
   const int Mt = G.Mt, W = G.W, SP = padded_len(G.Mt);
   bool finite;
-  const float scale = spread_scale(absmax, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave,
-                                   finite);
+  const float scale = spread_scale(G, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave, finite);
   const float inv = scale > 0.0f ? 1.0f / scale : 0.0f;
   const float bad = finite ? 0.0f : __int_as_float(0x7fc00000);
-  const int q0 = band_chunk[band], q1 = band_chunk[band + 1];
+  const int q0 = L.band_chunk[band], q1 = L.band_chunk[band + 1];
   for (int idx = threadIdx.x; idx < npair * Mt; idx += kNtBand) {
     const int p = idx / Mt;
     const int m = idx - p * Mt;
@@ -168,7 +198,7 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(
       // exact integer sums (two's complement, so order does not matter)
       int a = 0, b = 0;
       for (int q = q0; q < q1; ++q) {
-        const int* part = Hp + static_cast<size_t>(q) * G.R * W;
+        const int* part = G.Hp + static_cast<size_t>(q) * G.R * W;
         a += part[(2 * p) * W + c];
         b += part[(2 * p + 1) * W + c];
       }
@@ -178,8 +208,9 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(
     lds[p * SP + lpad(m)] = make_float2(lo + bad, hi + bad);
   }
   __syncthreads();
-  fft_rows<kNtBand, kInplaceValues, false>(lds, SP, npair, fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
-                           G.row_group, F, s_tw);
+  fft_rows<kNtBand, kInplaceValues, false>(lds, SP, npair,
+                                           fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
+                                           G.row_group, G.ft, s_tw);
   // two real rows per complex sequence: X1 = (Z[k] + conj Z[-k])/2,
   // X2 = (Z[k] - conj Z[-k])/(2i); keep k1 < K1
   for (int idx = threadIdx.x; idx < G.K1 * npair; idx += kNtBand) {
@@ -189,25 +220,27 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(
     const float2 Zm = lds[p * SP + lpad(k == 0 ? 0 : Mt - k)];
     const float4 o = make_float4(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y),
                                  0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
-    *reinterpret_cast<float4*>(S + static_cast<size_t>(k) * G.Mr + n0 + 2 * p) = o;
+    *reinterpret_cast<float4*>(G.S + static_cast<size_t>(k) * G.Mr + n0 + 2 * p) = o;
   }
 }
 
-// Column pass: col_batch kept k1 columns per workgroup: FFT along the log
-// radius, multiply by K (conj K for the adjoint; K(k1, -k2) = conj K(k1, k2)),
-// normalise, inverse FFT; only the used rows [u0, u1) come from and go back
-// to S.  Dynamic LDS: the columns, then the FFT scratch (if any).
-template <bool ADJ>
-__global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo G, FftDev F,
-                                                   const float2* __restrict__ tw,
-                                                   float2* __restrict__ S,
-                                                   const float2* __restrict__ K) {
+// Column pass (item i = columns [i col_batch, (i+1) col_batch) of the kept
+// k1): FFT along the log radius, multiply by K (conj K for the adjoint;
+// K(k1, -k2) = conj K(k1, k2)), normalise, inverse FFT; only the used rows
+// [u0, u1) come from and go back to S.  Dynamic LDS: the columns, then the
+// FFT scratch (if any).
+template <bool ADJ, bool BATCH>
+__global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo one, const DevGeo* __restrict__ geos,
+                                                      const int2* __restrict__ items) {
   extern __shared__ float2 lds[];
   __shared__ float2 s_tw[kTwLds];
-  load_twiddles<kNtCol>(s_tw, tw, G.Mr);
-  const int c0 = blockIdx.x * G.col_batch;
+  const Work w = work_item<BATCH>(one, geos, items);
+  const DevGeo& G = w.G;
+  load_twiddles<kNtCol>(s_tw, G.tw_r, G.Mr);
+  const int c0 = w.i * G.col_batch;
   const int nc = min(G.col_batch, G.K1 - c0);
   const int Mr = G.Mr, SP = padded_len(G.Mr);
+  float2* S = G.S;
   for (int i = threadIdx.x; i < nc * Mr; i += kNtCol) {
     const int c = i / Mr;
     const int n = i - c * Mr;
@@ -216,7 +249,7 @@ __global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo G, FftDev F,
   }
   __syncthreads();
   float2* cscr = G.col_inplace ? nullptr : lds + SP;
-  fft_rows<kNtCol, kInplaceValues, false>(lds, SP, nc, cscr, nc, F, s_tw);
+  fft_rows<kNtCol, kInplaceValues, false>(lds, SP, nc, cscr, nc, G.fr, s_tw);
   for (int i = threadIdx.x; i < nc * Mr; i += kNtCol) {
     const int c = i / Mr;
     const int n = i - c * Mr;
@@ -224,14 +257,14 @@ __global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo G, FftDev F,
     const int ak = k < 0 ? -k : k;
     float2 v = make_float2(0.f, 0.f);
     if (ak < G.K2) {
-      float2 kv = K[static_cast<size_t>(c0 + c) * G.K2 + ak];
+      float2 kv = G.K[static_cast<size_t>(c0 + c) * G.K2 + ak];
       if ((k < 0) != ADJ) kv.y = -kv.y;
       v = cscale(cmul(lds[c * SP + lpad(n)], kv), G.knorm);
     }
     lds[c * SP + lpad(n)] = v;
   }
   __syncthreads();
-  fft_rows<kNtCol, kInplaceValues, true>(lds, SP, nc, cscr, nc, F, s_tw);
+  fft_rows<kNtCol, kInplaceValues, true>(lds, SP, nc, cscr, nc, G.fr, s_tw);
   const int U = G.u1 - G.u0;
   for (int i = threadIdx.x; i < nc * U; i += kNtCol) {
     const int c = i / U;
@@ -240,17 +273,20 @@ __global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo G, FftDev F,
   }
 }
 
-// Inverse row FFT of one band: Z = X1 + i X2 for rows (2p, 2p+1) with the
-// Hermitian completion Z[-k], inverse FFT along the angle, real rows to Cr
-// (window columns only).  Dynamic LDS: the pairs, then the FFT scratch.
-__global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo G, FftDev F,
-                                                     const float2* __restrict__ tw,
-                                                     const float2* __restrict__ S,
-                                                     float* __restrict__ Cr) {
+// Inverse row FFT of one band (item i = band i): Z = X1 + i X2 for rows
+// (2p, 2p+1) with the Hermitian completion Z[-k], inverse FFT along the
+// angle, real rows to Cr (window columns only).  Dynamic LDS: the pairs,
+// then the FFT scratch.
+template <bool BATCH>
+__global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo one,
+                                                        const DevGeo* __restrict__ geos,
+                                                        const int2* __restrict__ items) {
   extern __shared__ float2 lds[];
   __shared__ float2 s_tw[kTwLds];
-  const int band = blockIdx.x;
-  load_twiddles<kNtBand>(s_tw, tw, G.Mt);
+  const Work w = work_item<BATCH>(one, geos, items);
+  const DevGeo& G = w.G;
+  const int band = w.i;
+  load_twiddles<kNtBand>(s_tw, G.tw_t, G.Mt);
   const int n0 = G.u0 + band * G.R;
   const int nr = min(G.R, G.u1 - n0);
   const int npair = nr >> 1;
@@ -260,16 +296,17 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo G, FftDev F,
   for (int idx = threadIdx.x; idx < G.K1 * npair; idx += kNtBand) {
     const int k = idx / npair;
     const int p = idx - k * npair;
-    const float4 x = *reinterpret_cast<const float4*>(S + static_cast<size_t>(k) * G.Mr + n0 +
+    const float4 x = *reinterpret_cast<const float4*>(G.S + static_cast<size_t>(k) * G.Mr + n0 +
                                                       2 * p);
     // X1 = (x.x, x.y), X2 = (x.z, x.w)
     lds[p * SP + lpad(k)] = make_float2(x.x - x.w, x.y + x.z);
     if (k > 0) lds[p * SP + lpad(Mt - k)] = make_float2(x.x + x.w, x.z - x.y);
   }
   __syncthreads();
-  fft_rows<kNtBand, kInplaceValues, true>(lds, SP, npair, fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
-                          G.row_group, F, s_tw);
-  float* dst = Cr + static_cast<size_t>(n0 - G.u0) * W;
+  fft_rows<kNtBand, kInplaceValues, true>(lds, SP, npair,
+                                          fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
+                                          G.row_group, G.ft, s_tw);
+  float* dst = G.Cr + static_cast<size_t>(n0 - G.u0) * W;
   for (int idx = threadIdx.x; idx < npair * W; idx += kNtBand) {
     const int p = idx / W;
     const int c = idx - p * W;
@@ -279,33 +316,36 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo G, FftDev F,
   }
 }
 
-// Gather for one chunk of a band's owned list (MODE 0: into g[nq][ntau];
-// MODE 1: into f[nx][nt], plus zeros outside the trapezoid, traces dealt
-// over the chunks).  Dynamic LDS: rows [L0, L1) of Cr, the band's rows and
-// the halo its points' stencils reach.  One point per thread, consecutive
-// threads on consecutive entries.
-template <int MODE>
-__global__ __launch_bounds__(kNtBand) void k_gather(
-    DevGeo G, const float* __restrict__ Cr, const uint4* __restrict__ ent,
-    const int64_t* __restrict__ chunk_off, const int* __restrict__ chunk_band,
-    int nchunks, float* __restrict__ out) {
+// Gather for one chunk of a band's owned list (item i = chunk i; MODE 0:
+// into g[nq][ntau]; MODE 1: into f[nx][nt], plus zeros outside the
+// trapezoid, traces dealt over the chunks).  Dynamic LDS: rows [L0, L1) of
+// Cr, the band's rows and the halo its points' stencils reach.  One point per
+// thread, consecutive threads on consecutive entries.
+template <int MODE, bool BATCH>
+__global__ __launch_bounds__(kNtBand) void k_gather(DevGeo one, const DevGeo* __restrict__ geos,
+                                                    const int2* __restrict__ items,
+                                                    float* __restrict__ out_base) {
   extern __shared__ float rows[];
-  const int chunk = blockIdx.x;
-  const int band = chunk_band[chunk];
+  const Work w = work_item<BATCH>(one, geos, items);
+  const DevGeo& G = w.G;
+  const DevList& L = G.lists[MODE == 0 ? kRadonOwn : kDataOwn];
+  float* out = out_base + (MODE == 0 ? G.radon_off : G.data_off);
+  const int chunk = w.i;
+  const int band = L.chunk_band[chunk];
   const int n0 = G.u0 + band * G.R;
   const int nr = min(G.R, G.u1 - n0);
   const int L0 = max(G.u0, n0 - 1);
   const int L1 = min(G.u1, n0 + nr + 2);
   const int W = G.W;
-  const float4* src = reinterpret_cast<const float4*>(Cr + static_cast<size_t>(L0 - G.u0) * W);
+  const float4* src = reinterpret_cast<const float4*>(G.Cr + static_cast<size_t>(L0 - G.u0) * W);
   float4* rows4 = reinterpret_cast<float4*>(rows);
   for (int i = threadIdx.x; i < (L1 - L0) * W / 4; i += kNtBand) rows4[i] = src[i];
   __syncthreads();
-  const int64_t e0 = chunk_off[chunk], e1 = chunk_off[chunk + 1];
+  const int64_t e0 = L.chunk_off[chunk], e1 = L.chunk_off[chunk + 1];
   const int shift = n0 - L0;  // held row of lattice row n0
   const int nheld = L1 - L0;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += kNtBand) {
-    const uint4 E = ent[e];
+    const uint4 E = L.ent[e];
     const EntryTaps tp = decode_entry(E.y, E.z, G.x_frac_bits);
     float acc = 0.0f;
 #pragma unroll
@@ -318,7 +358,7 @@ __global__ __launch_bounds__(kNtBand) void k_gather(
     out[E.x] = __uint_as_float(E.w) * acc;
   }
   if (MODE == 1) {
-    for (int k = chunk; k < G.nx; k += nchunks) {
+    for (int k = chunk; k < G.nx; k += L.nchunks) {
       float* fk = out + static_cast<size_t>(k) * G.nt;
       for (int j = threadIdx.x; j < G.jmin[k]; j += kNtBand) fk[j] = 0.0f;
     }

@@ -234,6 +234,75 @@ def ista(plan: Plan, f: torch.Tensor, mask=None, iters: int = 100, mu: float = 0
     return g
 
 
+class Batch:
+    """Uneven batch of gathers transformed by one launch per kernel; arrays
+    are packed 1-D float32 tensors (see offsets)."""
+
+    def __init__(self, descs, device=None):
+        self._lib = _lib.load()
+        self.descs = list(descs)
+        n = len(self.descs)
+        self.device = torch.device("cuda", torch.cuda.current_device()
+                                   if device is None else torch.device(device).index)
+        arr = (_lib.HrtDesc * n)(*[_lib.make_desc(d) for d in self.descs])
+        handle = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.hrt_batch_create(arr, n, C.byref(handle)), "hrt_batch_create")
+        self._h = handle
+        d_off = (C.c_int64 * (n + 1))()
+        r_off = (C.c_int64 * (n + 1))()
+        _lib.check(self._lib.hrt_batch_offsets(self._h, d_off, r_off), "hrt_batch_offsets")
+        self.data_off = list(d_off)
+        self.radon_off = list(r_off)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.hrt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, fn, x, out, n_in, n_out, stream, where):
+        if x.dtype != torch.float32 or not x.is_contiguous() or x.numel() != n_in \
+                or x.device != self.device:
+            raise ValueError(f"input must be a contiguous float32 tensor of {n_in} "
+                             f"elements on {self.device}")
+        if out is None:
+            out = torch.empty(n_out, dtype=torch.float32, device=self.device)
+        elif out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != n_out:
+            raise ValueError(f"out must be a contiguous float32 tensor of {n_out} elements")
+        _lib.check(fn(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+                      _stream_handle(stream)), where)
+        return out
+
+    def forward(self, f_packed, out=None, stream=None):
+        return self._call(self._lib.hrt_batch_forward, f_packed, out, self.data_off[-1],
+                          self.radon_off[-1], stream, "hrt_batch_forward")
+
+    def adjoint(self, g_packed, out=None, stream=None):
+        return self._call(self._lib.hrt_batch_adjoint, g_packed, out, self.radon_off[-1],
+                          self.data_off[-1], stream, "hrt_batch_adjoint")
+
+    def pack_data(self, fs):
+        return torch.cat([torch.as_tensor(f, dtype=torch.float32, device=self.device).reshape(-1)
+                          for f in fs])
+
+    def pack_radon(self, gs):
+        return self.pack_data(gs)
+
+    def unpack_data(self, packed):
+        return [packed[self.data_off[i]:self.data_off[i + 1]].view(d.nx, d.nt)
+                for i, d in enumerate(self.descs)]
+
+    def unpack_radon(self, packed):
+        return [packed[self.radon_off[i]:self.radon_off[i + 1]].view(d.nq, d.ntau)
+                for i, d in enumerate(self.descs)]
+
+
 class HRTFunction(torch.autograd.Function):
     """g = R_h f with backward grad_f = R_h^T grad_g (R_h is linear)."""
 
