@@ -29,9 +29,10 @@ METRIC = ("gathers/s fwd+adj at 2048x1024 FP32 vs GPU direct sum; "
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c3_traffic.json")
 CALIB_BYTES = 256 * 1024 * 1024       # the plain device copy of --calib-copy
-STAGE_KERNELS = ["k_absmax", "k_spread<0>", "k_rowfft<0>", "k_colfft<false>", "k_rowifft",
-                 "k_gather<0>", "k_absmax", "k_spread<1>", "k_rowfft<1>", "k_colfft<true>",
-                 "k_rowifft", "k_gather<1>"]
+STAGE_KERNELS = ["k_absmax<0, false>", "k_spread<0, false>", "k_rowfft<0, false>",
+                 "k_colfft<false, false>", "k_rowifft<false>", "k_gather<0, false>",
+                 "k_absmax<1, false>", "k_spread<1, false>", "k_rowfft<1, false>",
+                 "k_colfft<true, false>", "k_rowifft<false>", "k_gather<1, false>"]
 
 
 def log(msg):
@@ -204,6 +205,55 @@ def ista_c5(torch, np, iters=100, mu_rel=0.01):
             "snr_all_db": round(float(np.mean(snr_a)), 2), "hip_graph": True}
 
 
+def batch_c4(torch, np, n=64, reps=10):
+    """Uneven batch: n gathers (nt in {512, 1024, 2048}, nx in 128..1024),
+    forward+adjoint of the whole batch with one launch per kernel, against
+    the same gathers transformed one call at a time with the batch's own
+    plans (same kernels, same buffers)."""
+    import ctypes as C
+    import synth
+    from paper_1604_07651_amd.hrt import Batch
+    descs = synth.batch_descs(n, seed=4)
+    fs = synth.batch_gathers(descs)
+    b = Batch(descs)
+    F = b.pack_data(fs)
+    g = b.forward(F)
+    fa = b.adjoint(g)
+    plans = []
+    for i in range(n):
+        h = C.c_void_p()
+        b._lib.hrt_batch_plan(b._h, i, C.byref(h))
+        plans.append(h)
+    Fs, Gs, FAs = b.unpack_data(F), b.unpack_radon(g), b.unpack_data(fa)
+
+    def batched():
+        b.forward(F, out=g)
+        b.adjoint(g, out=fa)
+
+    def one_by_one():
+        s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        for i in range(n):
+            b._lib.hrt_forward(plans[i], C.c_void_p(Fs[i].data_ptr()),
+                               C.c_void_p(Gs[i].data_ptr()), s)
+            b._lib.hrt_adjoint(plans[i], C.c_void_p(Gs[i].data_ptr()),
+                               C.c_void_p(FAs[i].data_ptr()), s)
+
+    out = {"gathers": n, "samples": int(b.data_off[-1])}
+    for name, fn in (("batched", batched), ("per_gather", one_by_one)):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        out[name] = {"ms_per_batch": round(sec * 1e3, 3), "gathers_per_s": round(n / sec, 1)}
+    out["speedup"] = round(out["per_gather"]["ms_per_batch"] / out["batched"]["ms_per_batch"], 2)
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +262,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ista", action="store_true",
                     help="skip the trace-interpolation (soft-thresholding) run")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the uneven-batch run")
     ap.add_argument("--direct-steps", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (reference for "
@@ -328,6 +380,10 @@ def main():
                        "ms_fwd_adj": round(direct_sec * 1e3, 3),
                        "speedup_log_polar": round(direct_sec / sec_per_step, 1)},
     }
+
+    if not args.no_batch:
+        log("uneven batch: 64 gathers, one launch per kernel vs one call per gather")
+        out["batch_c4"] = batch_c4(torch, np)
 
     if not args.no_ista:
         log("trace interpolation: 16 gathers x 100 iterations in HIP graphs")

@@ -69,8 +69,16 @@ typedef struct {
   int32_t ntau, nq;    /* Radon samples: tau_i = tau0 + i*dtau, q_l = q0+l*dq */
   double tau0, dtau, q0, dq;
   double oversample;   /* log-polar oversampling sigma (2.0 is the default) */
-  int32_t flags;       /* reserved, must be 0                               */
+  int32_t flags;       /* HRT_TUNE_* bits (0: defaults); others must be 0    */
 } hrt_desc;
+
+/* Kernel variants, for tuning (results do not depend on them beyond float32
+ * rounding): FFT radices at most 8 along the angle / the log radius (default
+ * 16), two columns per workgroup in the column pass (default one). */
+#define HRT_TUNE_ROW_RADIX8 1
+#define HRT_TUNE_COL_RADIX8 2
+#define HRT_TUNE_COL_PAIRS 4
+#define HRT_TUNE_MASK 7
 
 /* What a plan computed (all host values). */
 typedef struct {

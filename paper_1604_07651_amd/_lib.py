@@ -104,11 +104,17 @@ def check(status: int, where: str) -> None:
         raise HrtError(status, where, detail or lib.hrt_status_string(status).decode())
 
 
-def make_desc(d) -> HrtDesc:
+# kernel-variant bits of hrt_desc.flags (HRT_TUNE_* in hrt.h)
+TUNE_ROW_RADIX8 = 1
+TUNE_COL_RADIX8 = 2
+TUNE_COL_PAIRS = 4
+
+
+def make_desc(d, flags: int = 0) -> HrtDesc:
     """HrtDesc from any object with the grid attributes (nt, nx, dt, x0, dx,
     ntau, nq, tau0, dtau, q0, dq, oversample)."""
     return HrtDesc(nt=int(d.nt), nx=int(d.nx), dt=float(d.dt), x0=float(d.x0),
                    dx=float(d.dx), ntau=int(d.ntau), nq=int(d.nq),
                    tau0=float(d.tau0), dtau=float(d.dtau), q0=float(d.q0),
                    dq=float(d.dq), oversample=float(getattr(d, "oversample", 2.0)),
-                   flags=0)
+                   flags=int(flags))

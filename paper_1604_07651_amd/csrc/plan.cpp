@@ -145,8 +145,8 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
     return fail(err, HRT_ERR_INVALID_ARG, "tau range exceeds the time range");
   if (!(d.oversample >= 1.5))
     return fail(err, HRT_ERR_INVALID_ARG, "oversampling must be >= 1.5");
-  if (d.flags != 0)
-    return fail(err, HRT_ERR_INVALID_ARG, "flags must be 0");
+  if (d.flags & ~HRT_TUNE_MASK)
+    return fail(err, HRT_ERR_INVALID_ARG, "unknown flags");
   if (static_cast<int64_t>(d.nt) * d.nx > (int64_t(1) << 31) ||
       static_cast<int64_t>(d.ntau) * d.nq > (int64_t(1) << 31))
     return fail(err, HRT_ERR_UNSUPPORTED, "panels above 2^31 samples");
@@ -346,8 +346,8 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   // FFT factorisations (needed by the LDS layout)
   if ((g.Mt + 63) / 64 + 64 > 256 || (g.Mr + 63) / 64 + 64 > 256)
     return fail(err, HRT_ERR_UNSUPPORTED, "lattice axis above 12288 points");
-  g.fft_t = factor_fft(g.Mt);
-  g.fft_r = factor_fft(g.Mr);
+  g.fft_t = factor_fft(g.Mt, (d.flags & HRT_TUNE_ROW_RADIX8) ? 8 : 16);
+  g.fft_r = factor_fft(g.Mr, (d.flags & HRT_TUNE_COL_RADIX8) ? 8 : 16);
   if (g.fft_t.npass < 0 || g.fft_r.npass < 0)
     return fail(err, HRT_ERR_GEOMETRY, "lattice size is not 5-smooth");
 
@@ -380,9 +380,9 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   if (layout(g.R, false) > lds_bytes)
     return fail(err, HRT_ERR_UNSUPPORTED, "angle axis too long for the LDS row bands");
   layout(g.R, true);
-  // one column per workgroup: two per workgroup (fewer, fuller
+  // one column per workgroup by default: two per workgroup (fewer, fuller
   // workgroups) measured slower at C3, the column pass being short of waves
-  g.col_batch = 1;
+  g.col_batch = (d.flags & HRT_TUNE_COL_PAIRS) ? 2 : 1;
   g.inplace_col = fft_fits_inplace(g.fft_r, g.col_batch, kColThreads, kInplaceValues);
   g.col_bytes = (g.inplace_col ? g.col_batch : 2) * padded_len(g.Mr) * 8;
   if (g.col_bytes > lds_bytes + kBandStaticLds)

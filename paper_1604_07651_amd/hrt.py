@@ -29,14 +29,20 @@ def _stream_handle(stream) -> C.c_void_p:
 class Plan:
     """A log-polar hyperbolic Radon transform plan on the current device."""
 
-    def __init__(self, desc, device=None):
+    def __init__(self, desc, device=None, flags: int = 0, tuned: bool = False):
+        """flags: HRT_TUNE_* kernel variants; tuned=True takes them from the
+        autotuner's cache (paper_1604_07651_amd.autotune) when it has them."""
+        if tuned:
+            from . import autotune
+            flags = autotune.tuned_flags(desc)
         self.desc = desc
+        self.flags = int(flags)
         self._lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device()
                                    if device is None else torch.device(device).index)
         handle = C.c_void_p()
         with torch.cuda.device(self.device):
-            _lib.check(self._lib.hrt_plan_create(C.byref(_lib.make_desc(desc)),
+            _lib.check(self._lib.hrt_plan_create(C.byref(_lib.make_desc(desc, self.flags)),
                                                  C.byref(handle)), "hrt_plan_create")
         self._h = handle
         info = _lib.HrtInfo()

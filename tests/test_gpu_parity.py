@@ -218,3 +218,32 @@ def test_unaligned_input_matches_aligned():
     b = plan.forward(F_off.clone())
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("flags", range(1, 8))
+def test_kernel_variants_match_oracle(flags):
+    """Every HRT_TUNE_* variant (smaller FFT radices, column pairs) on the
+    ragged grid against the oracle, to the same bar as the default."""
+    from paper_1604_07651_amd.hrt import Plan
+    desc, _, ora = setup("ragged")
+    plan = Plan(desc, flags=flags)
+    f, g = synth.random_pair(desc, 90 + flags)
+    print(f"[gpu] variant {flags}", flush=True)
+    compare(plan.forward(to_gpu(f)).cpu().numpy(), ora.forward(f), f"forward flags {flags}")
+    compare(plan.adjoint(to_gpu(g)).cpu().numpy(), ora.adjoint(g), f"adjoint flags {flags}")
+    plan.close()
+
+
+def test_autotuner_caches_and_plans_use_it(tmp_path, monkeypatch):
+    from paper_1604_07651_amd import autotune
+    from paper_1604_07651_amd.hrt import Plan
+    monkeypatch.setenv("HRT_TUNE_CACHE", str(tmp_path / "tune.json"))
+    desc = SMALL["c1"]
+    print("[gpu] autotune c1", flush=True)
+    res = autotune.tune(desc, reps=3)
+    assert set(res["ms"]) == {str(f) for f in autotune.VARIANTS}
+    assert res["flags"] == min(autotune.VARIANTS, key=lambda f: res["ms"][str(f)])
+    assert autotune.tuned_flags(desc) == res["flags"]
+    plan = Plan(desc, tuned=True)
+    assert plan.flags == res["flags"]
+    plan.close()

@@ -85,3 +85,13 @@ def test_status_strings_and_bad_handles():
     assert lib.hrt_forward(bogus, None, None, None) == 5
     assert lib.hrt_query(None, None) == 1
     lib.hrt_plan_destroy(bogus)   # ignored
+
+
+def test_describe_accepts_tuning_flags_and_rejects_others():
+    lib = _lib.load()
+    info = _lib.HrtInfo()
+    d = synth.config_desc("c1")
+    for fl in range(8):
+        assert lib.hrt_plan_describe(C.byref(_lib.make_desc(d, fl)), C.byref(info)) == 0
+    assert lib.hrt_plan_describe(C.byref(_lib.make_desc(d, 8)), C.byref(info)) == 1
+    assert lib.hrt_plan_describe(C.byref(_lib.make_desc(d, -1)), C.byref(info)) == 1
