@@ -201,6 +201,45 @@ hrt_status hrt_batch_adjoint(hrt_batch_t batch, const float* g_packed, float* f_
 hrt_status hrt_batch_plan(hrt_batch_t batch, int32_t i, hrt_plan_t* out);
 void hrt_batch_destroy(hrt_batch_t batch);
 
+/* Splitting into parts (Section 4, eq. tsplit: the integral over t cut at
+ * intermediate times, so that each part gets the log-polar lattice its own
+ * samples need; Section 5 applies the same to the slowness range).  The
+ * time samples are cut into n_t bands [t_edges[it], t_edges[it+1]) and the
+ * slowness rows into n_q bands [q_edges[iq], q_edges[iq+1]) (edges strictly
+ * increasing, t_edges[0] = 0, t_edges[n_t] = nt, q_edges[0] = 0,
+ * q_edges[n_q] = nq; 1 to 64 bands per axis).  Part iq*n_t + it is a plain
+ * problem of its own, rescaled by its own T and X (eq. hypnorm):
+ *   data   t_j, j < nt_p = min(nt, t_edges[it+1] + 2), only the samples of
+ *          its time band taken in; the traces with a kept sample in the band
+ *          (j dt >= q0_p x_k, q0_p = q0 + q_edges[iq] dq) plus one;
+ *   Radon  slowness rows of its band, tau_i <= (nt_p - 1) dt.
+ * The split transform is the sum of the parts' transforms, each placed in
+ * the whole arrays f float32[nx][nt] and g float32[nq][ntau]; a part's
+ * adjoint is its exact transpose, so the split adjoint is the transpose of
+ * the split forward.  One band per axis gives the plain transform.
+ * A part without a kept sample or a Radon sample is an error
+ * (HRT_ERR_INVALID_ARG), as is a part whose grids a plain plan rejects.
+ *
+ * hrt_split_describe: host only, no GPU; part `part`'s grid description
+ * (sub_out), its time band and slowness rows (window_out[4] = j_lo, j_hi,
+ * l_lo, l_hi) and its summary (info_out, computed only when non-null).
+ * hrt_split_create: one plan per part (as hrt_plan_create; the split owns
+ * them).  hrt_split_forward / hrt_split_adjoint enqueue the parts one after
+ * another on `stream` (every output sample is stored by one part and added
+ * to by the others); inputs and outputs must not overlap.  Calls on one
+ * split must not run concurrently. */
+typedef struct hrt_split_s* hrt_split_t;
+hrt_status hrt_split_describe(const hrt_desc* desc, int32_t n_t, const int32_t* t_edges,
+                              int32_t n_q, const int32_t* q_edges, int32_t part,
+                              hrt_desc* sub_out, int32_t* window_out, hrt_info* info_out);
+hrt_status hrt_split_create(const hrt_desc* desc, int32_t n_t, const int32_t* t_edges,
+                            int32_t n_q, const int32_t* q_edges, hrt_split_t* out);
+hrt_status hrt_split_forward(hrt_split_t split, const float* f, float* g, void* stream);
+hrt_status hrt_split_adjoint(hrt_split_t split, const float* g, float* f, void* stream);
+/* Copy of part `part`'s summary. */
+hrt_status hrt_split_query(hrt_split_t split, int32_t part, hrt_info* out);
+void hrt_split_destroy(hrt_split_t split);
+
 /* Copy of the plan's summary. */
 hrt_status hrt_query(hrt_plan_t plan, hrt_info* out);
 

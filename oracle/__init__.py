@@ -19,8 +19,9 @@ convolutions in log-polar coordinates"):
 Supporting modules: `geometry` (rescaling, sector placement, coordinate maps,
 lattice sizing), `bspline` (cubic cardinal B-spline), `kernel` (the spectrum of
 zeta by quadrature), `ista` (soft-thresholding iterations of Section 3),
-`demultiple` (Radon-domain multiple attenuation of Section 6).
+`demultiple` (Radon-domain multiple attenuation of Section 6), `split`
+(the transform cut into parts in time and slowness, Sections 4 and 5).
 All arithmetic is float64.  Readings of points where the paper is silent or
 garbled are stated in each function's docstring.
 """
-from . import bspline, geometry, kernel, logpolar, direct, ista, demultiple  # noqa: F401
+from . import bspline, geometry, kernel, logpolar, direct, ista, demultiple, split  # noqa: F401

@@ -37,6 +37,10 @@ Readings (the paper is silent or garbled):
 * R9  Spacing: dtheta0, drho0 are the literal maxima of eq. lpsamples over
       neighbour pairs with both samples kept; the lattice uses
       dtheta = dtheta0/sigma, drho = drho0/sigma, sigma the oversampling.
+* R11 A part of a split (Section 4, eq. tsplit) takes in only the data
+      samples of its time band [j_lo, j_hi): the kept set is the trapezoid
+      intersected with the band, everywhere above (maxima of eq. lpsamples,
+      smear weights, kept points).
 * R10 Extent: beta_k = beta + 4 dtheta; M_theta = smallest even 5-smooth
       integer >= ceil(2 beta_k/dtheta) + 1; M_rho = smallest even 5-smooth
       integer >= ceil((|ln a_r| + |ln cos beta_k|)/drho) + 9.  Node m sits at
@@ -171,8 +175,10 @@ def validate(desc) -> None:
         raise ValueError("oversampling must be >= 1.5")
 
 
-def build(desc) -> Geometry:
-    """Everything of Sections 2.1, 2.2 and 4 that depends only on the grids."""
+def build(desc, window=None) -> Geometry:
+    """Everything of Sections 2.1, 2.2 and 4 that depends only on the grids;
+    `window` = (j_lo, j_hi) restricts the kept data samples to a time band
+    (reading R11)."""
     validate(desc)
     T = (desc.nt - 1) * desc.dt
     X = desc.x0 + (desc.nx - 1) * desc.dx
@@ -190,6 +196,9 @@ def build(desc) -> Geometry:
     u, v = map_T(s, y, alpha, a, O1, O2)
     phi, eta = map_P1(u, v)
     keep = kept_mask(desc)
+    if window is not None:
+        j = np.arange(desc.nt)
+        keep = keep & ((j >= window[0]) & (j < window[1]))[None, :]
 
     # smear weight, reading R8
     dth = desc.dt / T

@@ -70,9 +70,9 @@ class LogPolarOracle:
     """Plan (geometry, kernel multiplier, point coordinates) plus forward and
     adjoint of the plain method for one grid description."""
 
-    def __init__(self, desc, n_panels: int | None = None):
+    def __init__(self, desc, n_panels: int | None = None, window=None):
         self.desc = desc
-        g = self.geo = geometry.build(desc)
+        g = self.geo = geometry.build(desc, window)
         self.K = kernel.kernel_full(g, n_panels)
         # data points inside the trapezoid, in lattice units
         self.kept = np.nonzero(g.keep)

@@ -66,6 +66,16 @@ SIGNATURES = [
     ("hrt_batch_adjoint", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("hrt_batch_plan", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     ("hrt_batch_destroy", None, [C.c_void_p]),
+    ("hrt_split_describe", C.c_int, [C.POINTER(HrtDesc), C.c_int32, C.POINTER(C.c_int32),
+                                     C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                     C.POINTER(HrtDesc), C.POINTER(C.c_int32),
+                                     C.POINTER(HrtInfo)]),
+    ("hrt_split_create", C.c_int, [C.POINTER(HrtDesc), C.c_int32, C.POINTER(C.c_int32),
+                                   C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_void_p)]),
+    ("hrt_split_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hrt_split_adjoint", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hrt_split_query", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(HrtInfo)]),
+    ("hrt_split_destroy", None, [C.c_void_p]),
     ("hrt_plan_destroy", None, [C.c_void_p]),
     ("hrt_status_string", C.c_char_p, [C.c_int]),
     ("hrt_last_error", C.c_char_p, []),

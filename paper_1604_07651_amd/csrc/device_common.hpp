@@ -42,6 +42,12 @@ struct DevGeo {
   float cmax_data, cmax_radon;  // bounds of the accumulated cells per unit input
   int absmax_blocks;            // partial maxima of this gather's input
   int64_t data_off, radon_off;  // this gather's offsets in packed batch arrays
+  // placement of a part of a split gather (whole grids: data_ld = nt,
+  // radon_ld = ntau, j_lo = 0, j_hi = nt, radon_row0 = 0, nx_fill = nx):
+  // row strides of the arrays, the data band [j_lo, j_hi) the part takes
+  // in, its first slowness row, the traces the adjoint's zero fill covers
+  int data_ld, radon_ld, j_lo, j_hi, radon_row0, nx_fill;
+  int accumulate;               // the gathers add into the output
   FftDev ft, fr;                // angle and log-radius FFTs
   const float2* tw_t;
   const float2* tw_r;
@@ -50,7 +56,7 @@ struct DevGeo {
   int* Hp;                      // spread partial rows [chunk][R][W]
   float* Cr;                    // real rows after the inverse row FFT [u1-u0][W]
   float* absmax;                // absmax_blocks partial maxima
-  const int* jmin;              // first kept time sample of each trace
+  const int* jmin;              // [nx_fill] first kept time sample of each trace
   DevList lists[4];
 };
 

@@ -32,6 +32,7 @@ namespace hrt {
 constexpr uint64_t kMagic = 0x6872745f706c616eull;
 constexpr uint64_t kGraphMagic = 0x6872745f67726170ull;
 constexpr uint64_t kBatchMagic = 0x6872745f62617463ull;
+constexpr uint64_t kSplitMagic = 0x6872745f73706c74ull;
 static_assert(kTwLds * sizeof(float2) + kNtBand / 64 * sizeof(float) <= kBandStaticLds,
               "static LDS");
 static_assert(sizeof(PointEntry) == sizeof(uint4), "point entry layout");
@@ -270,7 +271,9 @@ hrt_status hrt_plan_describe(const hrt_desc* desc, hrt_info* out) {
   return HRT_OK;
 }
 
-hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
+// A plan for the grids of `desc`, placed in the caller's arrays by `view`
+// (null: the whole grids).
+static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_plan_t* out) {
   if (!desc || !out) return set_err(HRT_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
   int dev = 0;
@@ -288,12 +291,16 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
   p->magic = kMagic;
   p->device = dev;
   std::string err;
-  hrt_status s = build_geometry(*desc, lds, p->g, err);
+  hrt_status s = build_geometry(*desc, lds, p->g, err, view);
   if (s != HRT_OK) {
     delete p;
     return set_err(s, err);
   }
   const Geometry& g = p->g;
+  // first kept sample of every trace of the data array (none beyond the
+  // plan's traces)
+  std::vector<int32_t> jmin_fill(g.jmin);
+  jmin_fill.resize(static_cast<size_t>(g.view.nx_fill), g.d.nt);
   if (static_cast<int64_t>(g.col_bytes) > std::min<int64_t>(lds_max, 163840) - 4096) {
     delete p;
     return set_err(HRT_ERR_UNSUPPORTED, "log-radius axis too long for an LDS column");
@@ -305,11 +312,11 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
       (s = dev_alloc(&p->K, static_cast<size_t>(g.K1) * g.K2, total)) ||
       (s = dev_alloc(&p->tw_t, twt.size(), total)) ||
       (s = dev_alloc(&p->tw_r, twr.size(), total)) ||
-      (s = dev_alloc(&p->jmin, g.d.nx, total)) ||
+      (s = dev_alloc(&p->jmin, jmin_fill.size(), total)) ||
       (s = dev_alloc(&p->absmax, kAbsMaxBlocks, total)) ||
       (s = dev_alloc(&p->dot, kDotBlocks, total)) ||
       (s = upload(p->tw_t, twt)) || (s = upload(p->tw_r, twr)) ||
-      (s = upload(p->jmin, g.jmin))) {
+      (s = upload(p->jmin, jmin_fill))) {
     free_plan(p);
     delete p;
     return s;
@@ -452,6 +459,10 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
   G.ntau = g.d.ntau; G.nq = g.d.nq;
   G.absmax_blocks = kAbsMaxBlocks;
   G.data_off = 0; G.radon_off = 0;
+  G.data_ld = g.view.data_ld; G.radon_ld = g.view.radon_ld;
+  G.j_lo = g.view.j_lo; G.j_hi = g.view.j_hi;
+  G.radon_row0 = g.view.radon_row0; G.nx_fill = g.view.nx_fill;
+  G.accumulate = 0;
   G.ft = p->ft; G.fr = p->fr;
   G.tw_t = p->tw_t; G.tw_r = p->tw_r;
   G.K = p->K; G.S = p->S; G.Hp = p->Hp; G.Cr = p->Cr; G.absmax = p->absmax;
@@ -504,6 +515,10 @@ hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
   return HRT_OK;
 }
 
+hrt_status hrt_plan_create(const hrt_desc* desc, hrt_plan_t* out) {
+  return create_plan(desc, nullptr, out);
+}
+
 namespace {
 // Records the profiling events around one kernel launch (no-op unless a
 // profile is active and has room).
@@ -524,25 +539,15 @@ struct StageTimer {
 };
 }  // namespace
 
-static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* stream,
-                               bool adjoint) {
-  hrt_status s = check_plan(p);
-  if (s != HRT_OK) return s;
-  if (!in || !out) return set_err(HRT_ERR_INVALID_ARG, "null array");
-  const size_t n_data = static_cast<size_t>(p->g.d.nx) * p->g.d.nt;
-  const size_t n_radon = static_cast<size_t>(p->g.d.nq) * p->g.d.ntau;
-  const size_t n_in = adjoint ? n_radon : n_data;
-  const size_t n_out = adjoint ? n_data : n_radon;
-  const char* ib = reinterpret_cast<const char*>(in);
-  const char* ob = reinterpret_cast<const char*>(out);
-  if (ib < ob + n_out * sizeof(float) && ob < ib + n_in * sizeof(float))
-    return set_err(HRT_ERR_INVALID_ARG, "input and output overlap");
-  DeviceGuard guard(p->device);
-  (void)hipGetLastError();  // do not report an earlier, unrelated error
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+// The six launches of one direction on stream `st` (arguments checked by
+// the caller; the device current).  With `accumulate` the gather adds into
+// `out` (the parts of a split after the first).
+static void run_chain(hrt_plan_t p, const float* in, float* out, hipStream_t st, bool adjoint,
+                      bool accumulate) {
   const Geometry& g = p->g;
   const size_t sb = g.spread_bytes, rb = g.row_bytes, cb = g.col_bytes, gb = g.gather_bytes;
-  const DevGeo& G = p->dg;
+  DevGeo G = p->dg;
+  G.accumulate = accumulate ? 1 : 0;
   const int* ni = p->nitems;
   const int t0 = adjoint ? 6 : 0;  // profile slots
   if (!adjoint) {
@@ -572,6 +577,24 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
     { StageTimer t(p, st, t0 + 5);
       k_gather<1, false><<<ni[kItGatherData], kNtBand, gb, st>>>(G, nullptr, nullptr, out); }
   }
+}
+
+static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* stream,
+                               bool adjoint) {
+  hrt_status s = check_plan(p);
+  if (s != HRT_OK) return s;
+  if (!in || !out) return set_err(HRT_ERR_INVALID_ARG, "null array");
+  const size_t n_data = static_cast<size_t>(p->g.d.nx) * p->g.d.nt;
+  const size_t n_radon = static_cast<size_t>(p->g.d.nq) * p->g.d.ntau;
+  const size_t n_in = adjoint ? n_radon : n_data;
+  const size_t n_out = adjoint ? n_data : n_radon;
+  const char* ib = reinterpret_cast<const char*>(in);
+  const char* ob = reinterpret_cast<const char*>(out);
+  if (ib < ob + n_out * sizeof(float) && ob < ib + n_in * sizeof(float))
+    return set_err(HRT_ERR_INVALID_ARG, "input and output overlap");
+  DeviceGuard guard(p->device);
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
+  run_chain(p, in, out, reinterpret_cast<hipStream_t>(stream), adjoint, false);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, adjoint ? "adjoint launch" : "forward launch");
   return HRT_OK;
@@ -964,6 +987,149 @@ void hrt_batch_destroy(hrt_batch_t b) {
   DeviceGuard guard(b->device);
   (void)hipDeviceSynchronize();
   free_batch(b);
+}
+
+// ------------------------------------------------------------- splits --
+
+struct hrt_split_s {
+  uint64_t magic;
+  int device;
+  hrt_desc d;
+  int n_t = 0, n_q = 0;
+  std::vector<hrt_plan_t> parts;  // part iq * n_t + it
+};
+
+namespace {
+void free_split(hrt_split_s* sp) {
+  for (hrt_plan_t q : sp->parts) hrt_plan_destroy(q);
+  sp->magic = 0;
+  delete sp;
+}
+
+hrt_status check_split(hrt_split_t sp) {
+  if (!sp || sp->magic != kSplitMagic) return set_err(HRT_ERR_BAD_HANDLE, "bad split handle");
+  return HRT_OK;
+}
+}  // namespace
+
+hrt_status hrt_split_describe(const hrt_desc* desc, int32_t n_t, const int32_t* t_edges,
+                              int32_t n_q, const int32_t* q_edges, int32_t part,
+                              hrt_desc* sub_out, int32_t* window_out, hrt_info* info_out) {
+  if (!desc) return set_err(HRT_ERR_INVALID_ARG, "null argument");
+  hrt_desc sub;
+  PartView v;
+  std::string err;
+  hrt_status s = split_part(*desc, n_t, t_edges, n_q, q_edges, part, sub, v, err);
+  if (s != HRT_OK) return set_err(s, err);
+  if (sub_out) *sub_out = sub;
+  if (window_out) {
+    window_out[0] = v.j_lo;
+    window_out[1] = v.j_hi;
+    window_out[2] = v.radon_row0;
+    window_out[3] = v.radon_row0 + sub.nq;
+  }
+  if (info_out) {
+    Geometry g;
+    s = build_geometry(sub, 163840 - kBandStaticLds, g, err, &v);
+    if (s != HRT_OK) return set_err(s, err);
+    fill_info(g, info_out);
+  }
+  return HRT_OK;
+}
+
+hrt_status hrt_split_create(const hrt_desc* desc, int32_t n_t, const int32_t* t_edges,
+                            int32_t n_q, const int32_t* q_edges, hrt_split_t* out) {
+  if (!desc || !out) return set_err(HRT_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (n_t < 1 || n_q < 1 || n_t > 64 || n_q > 64)
+    return set_err(HRT_ERR_INVALID_ARG, "1 to 64 bands per axis");
+  auto* sp = new hrt_split_s();
+  sp->magic = kSplitMagic;
+  sp->d = *desc;
+  sp->n_t = n_t;
+  sp->n_q = n_q;
+  {
+    hipError_t e = hipGetDevice(&sp->device);
+    if (e != hipSuccess) {
+      free_split(sp);
+      return hip_err(e, "hipGetDevice");
+    }
+  }
+  for (int part = 0; part < n_t * n_q; ++part) {
+    hrt_desc sub;
+    PartView v;
+    std::string err;
+    hrt_status s = split_part(*desc, n_t, t_edges, n_q, q_edges, part, sub, v, err);
+    hrt_plan_t pl = nullptr;
+    if (s == HRT_OK) {
+      s = create_plan(&sub, &v, &pl);
+      err = g_last_error;
+    }
+    if (s != HRT_OK) {
+      free_split(sp);
+      return set_err(s, "part " + std::to_string(part) + ": " + err);
+    }
+    sp->parts.push_back(pl);
+  }
+  *out = sp;
+  return HRT_OK;
+}
+
+hrt_status hrt_split_query(hrt_split_t sp, int32_t part, hrt_info* out) {
+  hrt_status s = check_split(sp);
+  if (s != HRT_OK) return s;
+  if (!out || part < 0 || part >= static_cast<int32_t>(sp->parts.size()))
+    return set_err(HRT_ERR_INVALID_ARG, "null argument or part out of range");
+  *out = sp->parts[part]->info;
+  return HRT_OK;
+}
+
+static hrt_status split_chain(hrt_split_t sp, const float* in, float* out, void* stream,
+                              bool adjoint) {
+  hrt_status s = check_split(sp);
+  if (s != HRT_OK) return s;
+  if (!in || !out) return set_err(HRT_ERR_INVALID_ARG, "null array");
+  const size_t nd = static_cast<size_t>(sp->d.nx) * sp->d.nt * sizeof(float);
+  const size_t nr = static_cast<size_t>(sp->d.nq) * sp->d.ntau * sizeof(float);
+  if (overlaps(in, adjoint ? nr : nd, out, adjoint ? nd : nr))
+    return set_err(HRT_ERR_INVALID_ARG, "input and output overlap");
+  DeviceGuard guard(sp->device);
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int n_t = sp->n_t, n_q = sp->n_q;
+  if (!adjoint) {
+    // the last time band reaches every tau of its slowness rows: it stores,
+    // the earlier bands add
+    for (int iq = 0; iq < n_q; ++iq) {
+      run_chain(sp->parts[iq * n_t + n_t - 1], in, out, st, false, false);
+      for (int it = 0; it < n_t - 1; ++it) run_chain(sp->parts[iq * n_t + it], in, out, st, false, true);
+    }
+  } else {
+    // the time bands cover disjoint data samples; the first slowness band
+    // stores (and zero-fills) them, the others add
+    for (int it = 0; it < n_t; ++it) {
+      run_chain(sp->parts[it], in, out, st, true, false);
+      for (int iq = 1; iq < n_q; ++iq) run_chain(sp->parts[iq * n_t + it], in, out, st, true, true);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(e, adjoint ? "split adjoint launch" : "split forward launch");
+  return HRT_OK;
+}
+
+hrt_status hrt_split_forward(hrt_split_t sp, const float* f, float* g, void* stream) {
+  return split_chain(sp, f, g, stream, false);
+}
+
+hrt_status hrt_split_adjoint(hrt_split_t sp, const float* g, float* f, void* stream) {
+  return split_chain(sp, g, f, stream, true);
+}
+
+void hrt_split_destroy(hrt_split_t sp) {
+  if (!sp || sp->magic != kSplitMagic) return;
+  DeviceGuard guard(sp->device);
+  (void)hipDeviceSynchronize();
+  free_split(sp);
 }
 
 hrt_status hrt_query(hrt_plan_t p, hrt_info* out) {

@@ -46,10 +46,11 @@ __device__ __forceinline__ Work work_item(const DevGeo& one, const DevGeo* __res
   return Work{geos[it.x], it.y};
 }
 
-// Largest |x| of one gather's input (MODE 0: data, MODE 1: Radon) as
-// absmax_blocks partial maxima (no atomics and nothing to clear, so replays
-// are safe); item i is partial i.  A non-finite input makes its block report
-// +inf.  16-byte loads when the gather's array is 16-byte aligned.
+// Largest |x| of one gather's input (MODE 0: the data band, MODE 1: the
+// Radon rows) as absmax_blocks partial maxima (no atomics and nothing to
+// clear, so replays are safe); item i is partial i.  A non-finite input
+// makes its block report +inf.  A contiguous input takes 16-byte loads when
+// it is 16-byte aligned; the band of a part is read row by row.
 template <int MODE, bool BATCH>
 __global__ __launch_bounds__(256) void k_absmax(DevGeo one, const DevGeo* __restrict__ geos,
                                                 const int2* __restrict__ items,
@@ -57,15 +58,27 @@ __global__ __launch_bounds__(256) void k_absmax(DevGeo one, const DevGeo* __rest
   __shared__ float s_m[4];
   const Work w = work_item<BATCH>(one, geos, items);
   const DevGeo& G = w.G;
-  const float* x = in + (MODE == 0 ? G.data_off : G.radon_off);
-  const int64_t n = MODE == 0 ? static_cast<int64_t>(G.nx) * G.nt
-                              : static_cast<int64_t>(G.nq) * G.ntau;
+  const float* x = in + (MODE == 0 ? G.data_off + G.j_lo
+                                    : G.radon_off + static_cast<int64_t>(G.radon_row0) * G.radon_ld);
+  const int rows = MODE == 0 ? G.nx : G.nq;
+  const int cols = MODE == 0 ? G.j_hi - G.j_lo : G.ntau;
+  const int ld = MODE == 0 ? G.data_ld : G.radon_ld;
+  const int64_t n = cols == ld ? static_cast<int64_t>(rows) * cols : 0;
   float m = 0.0f;
   bool bad = false;
   const int64_t tid = static_cast<int64_t>(w.i) * blockDim.x + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(G.absmax_blocks) * blockDim.x;
   int64_t done = 0;
-  if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+  if (cols != ld) {
+    for (int r = w.i; r < rows; r += G.absmax_blocks) {
+      const float* xr = x + static_cast<int64_t>(r) * ld;
+      for (int c = threadIdx.x; c < cols; c += blockDim.x) {
+        const float v = fabsf(xr[c]);
+        bad |= !(v <= 3.0e38f);
+        m = fmaxf(m, v);
+      }
+    }
+  } else if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
     const float4* x4 = reinterpret_cast<const float4*>(x);
     const int64_t n4 = n / 4;
     for (int64_t i = tid; i < n4; i += stride) {
@@ -318,7 +331,9 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo one,
 
 // Gather for one chunk of a band's owned list (item i = chunk i; MODE 0:
 // into g[nq][ntau]; MODE 1: into f[nx][nt], plus zeros outside the
-// trapezoid, traces dealt over the chunks).  Dynamic LDS: rows [L0, L1) of
+// trapezoid, traces dealt over the chunks; a part of a split stores into
+// its place in the whole arrays, zero-fills only its data band, and with
+// `accumulate` adds to the output and fills nothing).  Dynamic LDS: rows [L0, L1) of
 // Cr, the band's rows and the halo its points' stencils reach.  One point per
 // thread, consecutive threads on consecutive entries.
 template <int MODE, bool BATCH>
@@ -355,12 +370,14 @@ __global__ __launch_bounds__(kNtBand) void k_gather(DevGeo one, const DevGeo* __
       const float* r = rows + rl * W + tp.cx;
       acc += tp.wy[bb] * (r[0] * tp.wx[0] + r[1] * tp.wx[1] + r[2] * tp.wx[2] + r[3] * tp.wx[3]);
     }
-    out[E.x] = __uint_as_float(E.w) * acc;
+    const float v = __uint_as_float(E.w) * acc;
+    out[E.x] = G.accumulate ? out[E.x] + v : v;
   }
-  if (MODE == 1) {
-    for (int k = chunk; k < G.nx; k += L.nchunks) {
-      float* fk = out + static_cast<size_t>(k) * G.nt;
-      for (int j = threadIdx.x; j < G.jmin[k]; j += kNtBand) fk[j] = 0.0f;
+  if (MODE == 1 && !G.accumulate) {
+    for (int k = chunk; k < G.nx_fill; k += L.nchunks) {
+      float* fk = out + static_cast<size_t>(k) * G.data_ld;
+      const int j1 = min(G.jmin[k], G.j_hi);
+      for (int j = G.j_lo + threadIdx.x; j < j1; j += kNtBand) fk[j] = 0.0f;
     }
   }
 }

@@ -133,8 +133,52 @@ static hrt_status fail(std::string& err, hrt_status s, const char* msg) {
   return s;
 }
 
+hrt_status split_part(const hrt_desc& d, int n_t, const int32_t* t_edges, int n_q,
+                      const int32_t* q_edges, int part, hrt_desc& sub, PartView& view,
+                      std::string& err) {
+  if (n_t < 1 || n_q < 1 || !t_edges || !q_edges)
+    return fail(err, HRT_ERR_INVALID_ARG, "a split needs at least one band per axis");
+  if (part < 0 || part >= n_t * n_q) return fail(err, HRT_ERR_INVALID_ARG, "no such part");
+  if (t_edges[0] != 0 || t_edges[n_t] != d.nt || q_edges[0] != 0 || q_edges[n_q] != d.nq)
+    return fail(err, HRT_ERR_INVALID_ARG, "band edges must start at 0 and end at nt / nq");
+  for (int i = 0; i < n_t; ++i)
+    if (t_edges[i + 1] <= t_edges[i])
+      return fail(err, HRT_ERR_INVALID_ARG, "time band edges must increase");
+  for (int i = 0; i < n_q; ++i)
+    if (q_edges[i + 1] <= q_edges[i])
+      return fail(err, HRT_ERR_INVALID_ARG, "slowness band edges must increase");
+  const int it = part % n_t, iq = part / n_t;
+  const int j_lo = t_edges[it], j_hi = t_edges[it + 1];
+  const int l_lo = q_edges[iq], l_hi = q_edges[iq + 1];
+  sub = d;
+  sub.nt = std::min(d.nt, j_hi + kPartMargin);
+  sub.q0 = d.q0 + static_cast<double>(l_lo) * d.dq;
+  sub.nq = l_hi - l_lo;
+  // traces with a kept sample (j dt >= q0 x_k) at some j < j_hi, plus one
+  // whose trapezoid weight in x is then that of an inner trace of the whole
+  // grid or multiplies nothing
+  const double t_last = static_cast<double>(j_hi - 1) * d.dt;
+  int nk = 0;
+  while (nk < d.nx && t_last >= sub.q0 * (d.x0 + static_cast<double>(nk) * d.dx)) ++nk;
+  sub.nx = std::min(d.nx, nk + 1);
+  const double t_end = static_cast<double>(sub.nt - 1) * d.dt;
+  int ni = 0;
+  while (ni < d.ntau && d.tau0 + static_cast<double>(ni) * d.dtau <= t_end) ++ni;
+  sub.ntau = ni;
+  if (nk == 0 || ni == 0)
+    return fail(err, HRT_ERR_INVALID_ARG, "a part holds no kept sample or no Radon sample");
+  view = PartView{};
+  view.j_lo = j_lo;
+  view.j_hi = j_hi;
+  view.data_ld = d.nt;
+  view.radon_ld = d.ntau;
+  view.radon_row0 = l_lo;
+  view.nx_fill = d.nx;
+  return HRT_OK;
+}
+
 hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
-                          std::string& err) {
+                          std::string& err, const PartView* view) {
   if (d.nt < 4 || d.nx < 4 || d.ntau < 4 || d.nq < 4)
     return fail(err, HRT_ERR_INVALID_ARG, "every grid needs at least 4 samples");
   if (!(d.dt > 0) || !(d.dx > 0) || !(d.dtau > 0) || !(d.dq > 0))
@@ -153,6 +197,18 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
 
   g = Geometry{};
   g.d = d;
+  if (view) g.view = *view;
+  PartView& v = g.view;
+  if (v.j_hi < 0) v.j_hi = d.nt;
+  if (v.data_ld == 0) v.data_ld = d.nt;
+  if (v.radon_ld == 0) v.radon_ld = d.ntau;
+  if (v.nx_fill == 0) v.nx_fill = d.nx;
+  if (v.j_lo < 0 || v.j_hi > d.nt || v.j_lo >= v.j_hi || v.data_ld < d.nt ||
+      v.radon_ld < d.ntau || v.radon_row0 < 0 || v.nx_fill < d.nx)
+    return fail(err, HRT_ERR_INVALID_ARG, "part placement outside the arrays");
+  if (static_cast<int64_t>(v.nx_fill) * v.data_ld >= (int64_t{1} << 31) ||
+      static_cast<int64_t>(v.radon_row0 + d.nq) * v.radon_ld >= (int64_t{1} << 31))
+    return fail(err, HRT_ERR_UNSUPPORTED, "more than 2^31 samples in one array");
   // eq. hypnorm: rescale to the unit square
   g.T = (d.nt - 1) * d.dt;
   g.X = d.x0 + (d.nx - 1) * d.dx;
@@ -212,11 +268,13 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
     const int k1 = static_cast<int>(static_cast<int64_t>(d.nx) * (w + 1) / nth);
     std::vector<double> pp(d.nt), pe(d.nt), cp(d.nt), ce(d.nt);
     // previous trace (k0 - 1) for the offset-neighbour differences
+    // kept samples of trace k inside the data band: [first(k), j_hi)
+    auto first = [&](int k) { return std::max(g.jmin[k], v.j_lo); };
     if (k0 > 0)
-      for (int j = g.jmin[k0 - 1]; j < d.nt; ++j) map(j, k0 - 1, pp[j], pe[j]);
+      for (int j = first(k0 - 1); j < v.j_hi; ++j) map(j, k0 - 1, pp[j], pe[j]);
     for (int k = k0; k < k1; ++k) {
-      const int jm = g.jmin[k];
-      for (int j = jm; j < d.nt; ++j) {
+      const int jm = first(k);
+      for (int j = jm; j < v.j_hi; ++j) {
         map(j, k, cp[j], ce[j]);
         s.eta_min = std::min(s.eta_min, ce[j]);
         s.eta_max = std::max(s.eta_max, ce[j]);
@@ -224,12 +282,12 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
           s.dphi = std::max(s.dphi, std::fabs(cp[j] - cp[j - 1]));
           s.deta = std::max(s.deta, std::fabs(ce[j] - ce[j - 1]));
         }
-        if (k > 0 && j >= g.jmin[k - 1]) {
+        if (k > 0 && j >= first(k - 1)) {
           s.dphi = std::max(s.dphi, std::fabs(cp[j] - pp[j]));
           s.deta = std::max(s.deta, std::fabs(ce[j] - pe[j]));
         }
       }
-      s.kept += d.nt - jm;
+      s.kept += std::max(0, v.j_hi - jm);
       std::swap(pp, cp);
       std::swap(pe, ce);
     }
@@ -445,6 +503,7 @@ void make_chunks(int nb, int max_entries, BandLists& L) {
 template <class PlaceF>
 hrt_status build_lists(const Geometry& g, int64_t npts, PlaceF place, BandLists& spread,
                        BandLists& own, std::string& err) {
+  // place(p, xg, yg, w, idx) also gives the index stored in the entry
   const int nb = g.nbands;
   unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   nth = static_cast<unsigned>(std::min<int64_t>(nth, std::max<int64_t>(1, npts / 4096)));
@@ -461,7 +520,8 @@ hrt_status build_lists(const Geometry& g, int64_t npts, PlaceF place, BandLists&
     const int64_t p0 = npts * w / nth, p1 = npts * (w + 1) / nth;
     for (int64_t p = p0; p < p1; ++p) {
       double xg, yg, wt;
-      if (!place(p, xg, yg, wt)) continue;
+      uint32_t idx = 0;
+      if (!place(p, xg, yg, wt, idx)) continue;
       const double fy = std::floor(yg);
       const int iy = static_cast<int>(fy);
       const double xr = xg - g.xw0;
@@ -475,7 +535,7 @@ hrt_status build_lists(const Geometry& g, int64_t npts, PlaceF place, BandLists&
       for (int b = b_lo; b <= b_hi; ++b) {
         if (!fill) { ++cs[w][b]; continue; }
         const double base = g.u0 + b * g.R - 2;
-        PointEntry e{static_cast<uint32_t>(p), xq,
+        PointEntry e{idx, xq,
                      static_cast<uint32_t>(std::llround((yg - base) * ys)),
                      static_cast<float>(wt)};
         spread.e[(*ps)[b]++] = e;
@@ -563,12 +623,14 @@ double list_cmax(const Geometry& g, const BandLists& L) {
 
 hrt_status build_point_tables(const Geometry& g, PointTables& t, std::string& err) {
   const hrt_desc& d = g.d;
+  const PartView& v = g.view;
   hrt_status s = build_lists(
       g, static_cast<int64_t>(d.nx) * d.nt,
-      [&](int64_t p, double& xg, double& yg, double& w) {
+      [&](int64_t p, double& xg, double& yg, double& w, uint32_t& idx) {
         const int k = static_cast<int>(p / d.nt), j = static_cast<int>(p % d.nt);
-        if (j < g.jmin[k]) return false;
+        if (j < g.jmin[k] || j < v.j_lo || j >= v.j_hi) return false;
         place_data(g, j, k, xg, yg, w);
+        idx = static_cast<uint32_t>(static_cast<int64_t>(k) * v.data_ld + j);
         return true;
       },
       t.data_spread, t.data_own, err);
@@ -580,8 +642,9 @@ hrt_status build_point_tables(const Geometry& g, PointTables& t, std::string& er
   }
   s = build_lists(
       g, static_cast<int64_t>(d.nq) * d.ntau,
-      [&](int64_t p, double& xg, double& yg, double& w) {
+      [&](int64_t p, double& xg, double& yg, double& w, uint32_t& idx) {
         const int l = static_cast<int>(p / d.ntau), i = static_cast<int>(p % d.ntau);
+        idx = static_cast<uint32_t>(static_cast<int64_t>(v.radon_row0 + l) * v.radon_ld + i);
         xg = qx[l];
         yg = radon_row(g, i, l);
         w = g.q_scale[l];

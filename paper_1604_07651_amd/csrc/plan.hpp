@@ -62,9 +62,37 @@ struct FftFactors {
 // Radices are taken largest first from kFftRadices, up to max_radix.
 FftFactors factor_fft(int n, int max_radix = 16);
 
+// Where a plan's grids sit in the caller's arrays, and the part of its data
+// grid it takes in (Section 4, eq. tsplit: the integral over t cut at
+// intermediate times).  The defaults are the whole grids in arrays
+// [nx][nt] and [nq][ntau].
+struct PartView {
+  int j_lo = 0, j_hi = -1;        // data samples j in [j_lo, j_hi) (-1: nt)
+  int data_ld = 0, radon_ld = 0;  // row strides of the two arrays (0: nt, ntau)
+  int radon_row0 = 0;             // the plan's first slowness row in the Radon array
+  int nx_fill = 0;                // traces of the data array (0: nx)
+};
+
+// Samples a part's data and Radon rows reach beyond its last time sample:
+// the reach of the cubic interpolation in time of the direct summation.
+constexpr int kPartMargin = 2;
+
+// The sub-problem of part `part` = iq * n_t + it of a split of the grids of
+// `d` into time bands [t_edges[it], t_edges[it + 1]) and slowness bands
+// [q_edges[iq], q_edges[iq + 1]) (Section 4, eq. tsplit, and the slowness
+// split of Section 5).  The part is a plain problem of its own: data
+// samples 0 .. min(nt, j_hi + kPartMargin) - 1 (rescaled by its own T) of
+// the traces that hold kept samples in its band plus one, its slowness rows,
+// and the Radon samples tau_i <= its last time; `view` places it in the
+// whole arrays and restricts its data samples to its band.
+hrt_status split_part(const hrt_desc& d, int n_t, const int32_t* t_edges, int n_q,
+                      const int32_t* q_edges, int part, hrt_desc& sub, PartView& view,
+                      std::string& err);
+
 // Everything the plan derives from the grids (Sections 2.1, 2.2, 4).
 struct Geometry {
   hrt_desc d{};
+  PartView view;              // resolved: no defaults left
   // eq. hypnorm
   double T = 0, X = 0;
   // Section 2.1: sector, square, first contribution
@@ -91,7 +119,7 @@ struct Geometry {
   // dynamic LDS per workgroup of the spread, row FFT, column and gather
   // kernels
   int spread_bytes = 0, row_bytes = 0, col_bytes = 0, gather_bytes = 0;
-  int64_t n_kept = 0;
+  int64_t n_kept = 0;          // kept samples inside the data band
   std::vector<int32_t> jmin;  // [nx] first kept time sample of each trace
   // Radon side, per slowness l
   std::vector<double> qA, qB;     // e^rho = qA + qB tau^2
@@ -102,7 +130,8 @@ struct Geometry {
 };
 
 // One point of a band's list, 16 bytes: the sample's linear index in its
-// array (k*nt + j for data, l*ntau + i for Radon), its lattice coordinates
+// array (k*data_ld + j for data, (radon_row0 + l)*radon_ld + i for Radon;
+// k*nt + j and l*ntau + i for a whole-grid plan), its lattice coordinates
 // in fixed point relative to the band (angle: column - xw0 with
 // x_frac_bits fraction bits; log radius: row - (n0 - 2) with kYFracBits
 // fraction bits, n0 the band's first row), and its weight (the smear weight
@@ -142,10 +171,11 @@ struct PointTables {
 hrt_status build_point_tables(const Geometry& g, PointTables& t, std::string& err);
 
 // Validates `d` and computes the geometry.  `lds_bytes` is the per-workgroup
-// LDS the band kernels may use (it bounds the band height).  Returns
-// HRT_OK or an error with a message in `err`.
+// LDS the band kernels may use (it bounds the band height).  With a `view`,
+// only data samples inside its band count (eq. lpsamples, the lattice rows,
+// the point lists).  Returns HRT_OK or an error with a message in `err`.
 hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
-                          std::string& err);
+                          std::string& err, const PartView* view = nullptr);
 
 // Algorithmic bytes of one forward / adjoint (per kernel: inputs read once,
 // outputs written once).

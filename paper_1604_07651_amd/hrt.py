@@ -309,6 +309,95 @@ class Batch:
                 for i, d in enumerate(self.descs)]
 
 
+def split_edges(desc, n_t: int = 2, n_q: int = 2, first: float = 0.375):
+    """Band edges for Split: time bands cut at the fractions first^(n_t-1),
+    ..., first^2, first of the time samples (the early bands the shortest:
+    they are where the Radon samples crowd on the lattice), slowness rows cut
+    into n_q equal bands."""
+    nt, nq = int(desc.nt), int(desc.nq)
+    cuts = sorted({int(round(nt * first ** k)) for k in range(1, n_t)})
+    t_edges = [0] + [c for c in cuts if 0 < c < nt] + [nt]
+    q_edges = [nq * i // n_q for i in range(n_q + 1)]
+    if len(set(q_edges)) != len(q_edges):
+        raise ValueError("more slowness bands than slowness rows")
+    return t_edges, q_edges
+
+
+def _edges(edges):
+    e = [int(v) for v in edges]
+    return len(e) - 1, (C.c_int32 * len(e))(*e)
+
+
+def describe_part(desc, t_edges, q_edges, part: int) -> dict:
+    """Host-only: part `part`'s grid (keys of the description), its bands
+    (j_lo, j_hi, l_lo, l_hi) and its plan summary (no GPU needed)."""
+    lib = _lib.load()
+    n_t, te = _edges(t_edges)
+    n_q, qe = _edges(q_edges)
+    sub = _lib.HrtDesc()
+    win = (C.c_int32 * 4)()
+    info = _lib.HrtInfo()
+    _lib.check(lib.hrt_split_describe(C.byref(_lib.make_desc(desc)), n_t, te, n_q, qe,
+                                      int(part), C.byref(sub), win, C.byref(info)),
+               "hrt_split_describe")
+    out = {name: getattr(sub, name) for name, _ in sub._fields_}
+    out.update(j_lo=win[0], j_hi=win[1], l_lo=win[2], l_hi=win[3], info=info.as_dict())
+    return out
+
+
+class Split(Plan):
+    """The transform cut into time and slowness bands (Section 4, eq.
+    tsplit; Section 5): one plan per part, each rescaled to its own grid, the
+    parts' results added into the whole arrays.  Same array shapes as Plan."""
+
+    def __init__(self, desc, t_edges, q_edges, device=None, flags: int = 0):
+        self.desc = desc
+        self.flags = int(flags)
+        self._lib = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device()
+                                   if device is None else torch.device(device).index)
+        self.t_edges = [int(v) for v in t_edges]
+        self.q_edges = [int(v) for v in q_edges]
+        n_t, te = _edges(self.t_edges)
+        n_q, qe = _edges(self.q_edges)
+        handle = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.hrt_split_create(C.byref(_lib.make_desc(desc, self.flags)),
+                                                  n_t, te, n_q, qe, C.byref(handle)),
+                       "hrt_split_create")
+        self._h = handle
+        self.n_parts = n_t * n_q
+        self.parts = []
+        for p in range(self.n_parts):
+            info = _lib.HrtInfo()
+            _lib.check(self._lib.hrt_split_query(self._h, p, C.byref(info)), "hrt_split_query")
+            self.parts.append(info.as_dict())
+        self.info = self.parts[-1]
+        self.data_shape = (int(desc.nx), int(desc.nt))
+        self.radon_shape = (int(desc.nq), int(desc.ntau))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.hrt_split_destroy(self._h)
+            self._h = None
+
+    def forward(self, f: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+        """g = sum over parts of the parts' forwards: f (nx, nt) -> g (nq, ntau)."""
+        return self._call(self._lib.hrt_split_forward, f, out, self.data_shape,
+                          self.radon_shape, stream, "hrt_split_forward")
+
+    def adjoint(self, g: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+        """The exact transpose of forward: g (nq, ntau) -> f (nx, nt)."""
+        return self._call(self._lib.hrt_split_adjoint, g, out, self.radon_shape,
+                          self.data_shape, stream, "hrt_split_adjoint")
+
+    def _unsupported(self, *a, **k):
+        raise NotImplementedError("not available on a split; use a Plan")
+
+    direct_forward = direct_adjoint = profile_begin = profile_end = kernel = _unsupported
+    ista_iterate = ista_graph = opnorm2 = demultiple = _unsupported
+
+
 class HRTFunction(torch.autograd.Function):
     """g = R_h f with backward grad_f = R_h^T grad_g (R_h is linear)."""
 

@@ -95,3 +95,43 @@ def test_describe_accepts_tuning_flags_and_rejects_others():
         assert lib.hrt_plan_describe(C.byref(_lib.make_desc(d, fl)), C.byref(info)) == 0
     assert lib.hrt_plan_describe(C.byref(_lib.make_desc(d, 8)), C.byref(info)) == 1
     assert lib.hrt_plan_describe(C.byref(_lib.make_desc(d, -1)), C.byref(info)) == 1
+
+
+SPLITS = [(synth.config_desc("c1"), [0, 64, 256], [0, 64, 128]),
+          (synth.config_desc("c1"), [0, 32, 96, 256], [0, 40, 80, 128]),
+          (DESCS[3], [0, 15, 37], [0, 9, 19]),
+          (synth.config_desc("c3"), [0, 768, 2048], [0, 512, 1024])]
+
+
+@pytest.mark.parametrize("desc,te,qe", SPLITS)
+def test_host_split_parts_match_oracle(desc, te, qe):
+    """hrt_split_describe derives every part (grid, bands, geometry) as the
+    oracle's independent split does."""
+    from oracle import split
+    from paper_1604_07651_amd import hrt
+    parts = split.parts(desc, te, qe)
+    for i, p in enumerate(parts):
+        got = hrt.describe_part(desc, te, qe, i)
+        for k in ("nt", "nx", "ntau", "nq", "q0", "dt", "dx", "x0", "tau0", "dtau", "dq"):
+            assert got[k] == getattr(p.desc, k), (i, k)
+        assert (got["j_lo"], got["j_hi"], got["l_lo"], got["l_hi"]) == (p.j_lo, p.j_hi, p.l_lo,
+                                                                         p.l_hi)
+        g = geometry.build(p.desc, (p.j_lo, p.j_hi))
+        info = got["info"]
+        for name, ref in [("T", g.T), ("X", g.X), ("beta", g.beta), ("a", g.a),
+                          ("dtheta0", g.dtheta0), ("drho0", g.drho0)]:
+            assert abs(info[name] - ref) <= 1e-13 * max(1.0, abs(ref)), (i, name)
+        assert (info["m_theta"], info["m_rho"]) == (g.Mtheta, g.Mrho)
+        assert info["n_kept"] == int(g.keep.sum())
+
+
+def test_host_split_rejects_bad_edges():
+    from paper_1604_07651_amd import hrt
+    d = synth.config_desc("c1")
+    for te, qe in [([0, 100, 90, 256], [0, 128]), ([0, 256], [1, 128]), ([0, 255], [0, 128]),
+                   ([0, 1, 256], [0, 128])]:
+        with pytest.raises(_lib.HrtError):
+            for i in range((len(te) - 1) * (len(qe) - 1)):
+                hrt.describe_part(d, te, qe, i)
+    with pytest.raises(_lib.HrtError):
+        hrt.describe_part(d, [0, 128, 256], [0, 128], 2)
