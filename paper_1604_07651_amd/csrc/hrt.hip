@@ -821,6 +821,7 @@ hrt_status hrt_direct_adjoint(hrt_plan_t p, const float* g, float* f, void* stre
 struct hrt_batch_s {
   uint64_t magic;
   int device;
+  bool owns_plans = true;
   std::vector<hrt_plan_t> plans;
   std::vector<int64_t> data_off, radon_off;  // n + 1 each, in floats
   DevGeo* geos = nullptr;                    // one descriptor per gather
@@ -834,9 +835,61 @@ void free_batch(hrt_batch_s* b) {
   if (b->geos) (void)hipFree(b->geos);
   for (int2* q : b->items)
     if (q) (void)hipFree(q);
-  for (hrt_plan_t q : b->plans) hrt_plan_destroy(q);
+  if (b->owns_plans)
+    for (hrt_plan_t q : b->plans) hrt_plan_destroy(q);
   b->magic = 0;
   delete b;
+}
+
+// Device tables of a batch whose plans, offsets (data_off, radon_off) and
+// LDS sizes are set: one descriptor per plan (gathers with `accumulate[i]`
+// add into their output) and the work items, largest gathers first so that
+// the small ones fill in at the end of each launch.
+hrt_status build_batch_tables(hrt_batch_s* b, const std::vector<int>& accumulate) {
+  const int n = static_cast<int>(b->plans.size());
+  std::vector<DevGeo> geos(n);
+  std::vector<int> order(n);
+  std::vector<int64_t> work(n);
+  for (int i = 0; i < n; ++i) {
+    const hrt_plan_s* pl = b->plans[i];
+    geos[i] = pl->dg;
+    geos[i].data_off = b->data_off[i];
+    geos[i].radon_off = b->radon_off[i];
+    geos[i].absmax_blocks = kAbsMaxBlocksBatch;
+    geos[i].accumulate = accumulate[i];
+    work[i] = static_cast<int64_t>(pl->g.d.nx) * pl->g.d.nt;
+    order[i] = i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+  std::vector<int2> it[kItemSets];
+  for (int i : order) {
+    const hrt_plan_s* pl = b->plans[i];
+    for (int k = 0; k < kAbsMaxBlocksBatch; ++k) it[kItAbsmax].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->nchunks[kDataSpread]; ++k) it[kItSpreadData].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->nchunks[kRadonSpread]; ++k)
+      it[kItSpreadRadon].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->g.nbands; ++k) it[kItBands].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->nitems[kItCols]; ++k) it[kItCols].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->nchunks[kRadonOwn]; ++k) it[kItGatherRadon].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->nchunks[kDataOwn]; ++k) it[kItGatherData].push_back(make_int2(i, k));
+  }
+  for (const hrt_plan_s* pl : b->plans) {
+    b->spread_bytes = std::max(b->spread_bytes, pl->g.spread_bytes);
+    b->row_bytes = std::max(b->row_bytes, pl->g.row_bytes);
+    b->col_bytes = std::max(b->col_bytes, pl->g.col_bytes);
+    b->gather_bytes = std::max(b->gather_bytes, pl->g.gather_bytes);
+  }
+  DeviceGuard guard(b->device);
+  size_t total = 0;
+  hrt_status s = HRT_OK;
+  if ((s = dev_alloc(&b->geos, n, total)) || (s = upload(b->geos, geos))) return s;
+  for (int k = 0; k < kItemSets; ++k) {
+    b->nitems[k] = static_cast<int>(it[k].size());
+    if ((s = dev_alloc(&b->items[k], std::max<size_t>(1, it[k].size()), total)) ||
+        (s = upload(b->items[k], it[k])))
+      return s;
+  }
+  return HRT_OK;
 }
 
 hrt_status check_batch(hrt_batch_t b) {
@@ -865,51 +918,11 @@ hrt_status hrt_batch_create(const hrt_desc* descs, int32_t n, hrt_batch_t* out) 
     const Geometry& g = pl->g;
     b->data_off[i + 1] = b->data_off[i] + static_cast<int64_t>(g.d.nx) * g.d.nt;
     b->radon_off[i + 1] = b->radon_off[i] + static_cast<int64_t>(g.d.nq) * g.d.ntau;
-    b->spread_bytes = std::max(b->spread_bytes, g.spread_bytes);
-    b->row_bytes = std::max(b->row_bytes, g.row_bytes);
-    b->col_bytes = std::max(b->col_bytes, g.col_bytes);
-    b->gather_bytes = std::max(b->gather_bytes, g.gather_bytes);
   }
-  // descriptors with the packed offsets; work items, largest gathers first so
-  // that the small ones fill in at the end of each launch
-  std::vector<DevGeo> geos(n);
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) {
-    geos[i] = b->plans[i]->dg;
-    geos[i].data_off = b->data_off[i];
-    geos[i].radon_off = b->radon_off[i];
-    geos[i].absmax_blocks = kAbsMaxBlocksBatch;
-    order[i] = i;
-  }
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return b->data_off[x + 1] - b->data_off[x] > b->data_off[y + 1] - b->data_off[y];
-  });
-  std::vector<int2> it[kItemSets];
-  for (int i : order) {
-    const hrt_plan_s* pl = b->plans[i];
-    for (int k = 0; k < kAbsMaxBlocksBatch; ++k) it[kItAbsmax].push_back(make_int2(i, k));
-    for (int k = 0; k < pl->nchunks[kDataSpread]; ++k) it[kItSpreadData].push_back(make_int2(i, k));
-    for (int k = 0; k < pl->nchunks[kRadonSpread]; ++k)
-      it[kItSpreadRadon].push_back(make_int2(i, k));
-    for (int k = 0; k < pl->g.nbands; ++k) it[kItBands].push_back(make_int2(i, k));
-    for (int k = 0; k < pl->nitems[kItCols]; ++k) it[kItCols].push_back(make_int2(i, k));
-    for (int k = 0; k < pl->nchunks[kRadonOwn]; ++k) it[kItGatherRadon].push_back(make_int2(i, k));
-    for (int k = 0; k < pl->nchunks[kDataOwn]; ++k) it[kItGatherData].push_back(make_int2(i, k));
-  }
-  DeviceGuard guard(b->device);
-  size_t total = 0;
-  hrt_status s = HRT_OK;
-  if ((s = dev_alloc(&b->geos, n, total)) || (s = upload(b->geos, geos))) {
+  hrt_status s = build_batch_tables(b, std::vector<int>(n, 0));
+  if (s != HRT_OK) {
     free_batch(b);
     return s;
-  }
-  for (int k = 0; k < kItemSets; ++k) {
-    b->nitems[k] = static_cast<int>(it[k].size());
-    if ((s = dev_alloc(&b->items[k], std::max<size_t>(1, it[k].size()), total)) ||
-        (s = upload(b->items[k], it[k]))) {
-      free_batch(b);
-      return s;
-    }
   }
   *out = b;
   return HRT_OK;
@@ -934,18 +947,9 @@ hrt_status hrt_batch_plan(hrt_batch_t b, int32_t i, hrt_plan_t* out) {
   return HRT_OK;
 }
 
-static hrt_status batch_chain(hrt_batch_t b, const float* in, float* out, void* stream,
-                              bool adjoint) {
-  hrt_status s = check_batch(b);
-  if (s != HRT_OK) return s;
-  if (!in || !out) return set_err(HRT_ERR_INVALID_ARG, "null array");
-  const size_t nd = static_cast<size_t>(b->data_off.back()) * sizeof(float);
-  const size_t nr = static_cast<size_t>(b->radon_off.back()) * sizeof(float);
-  if (overlaps(in, adjoint ? nr : nd, out, adjoint ? nd : nr))
-    return set_err(HRT_ERR_INVALID_ARG, "input and output overlap");
-  DeviceGuard guard(b->device);
-  (void)hipGetLastError();
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+// The six batched launches of one direction (arguments checked by the
+// caller; the device current).
+static void run_batch(hrt_batch_t b, const float* in, float* out, hipStream_t st, bool adjoint) {
   const DevGeo none{};
   const DevGeo* geo = b->geos;
   int2* const* it = b->items;
@@ -969,6 +973,20 @@ static hrt_status batch_chain(hrt_batch_t b, const float* in, float* out, void* 
     k_gather<1, true><<<ni[kItGatherData], kNtBand, gb, st>>>(none, geo, it[kItGatherData],
                                                               out);
   }
+}
+
+static hrt_status batch_chain(hrt_batch_t b, const float* in, float* out, void* stream,
+                              bool adjoint) {
+  hrt_status s = check_batch(b);
+  if (s != HRT_OK) return s;
+  if (!in || !out) return set_err(HRT_ERR_INVALID_ARG, "null array");
+  const size_t nd = static_cast<size_t>(b->data_off.back()) * sizeof(float);
+  const size_t nr = static_cast<size_t>(b->radon_off.back()) * sizeof(float);
+  if (overlaps(in, adjoint ? nr : nd, out, adjoint ? nd : nr))
+    return set_err(HRT_ERR_INVALID_ARG, "input and output overlap");
+  DeviceGuard guard(b->device);
+  (void)hipGetLastError();
+  run_batch(b, in, out, reinterpret_cast<hipStream_t>(stream), adjoint);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, adjoint ? "batch adjoint launch" : "batch forward launch");
   return HRT_OK;
@@ -997,10 +1015,16 @@ struct hrt_split_s {
   hrt_desc d;
   int n_t = 0, n_q = 0;
   std::vector<hrt_plan_t> parts;  // part iq * n_t + it
+  // the parts grouped into phases run one after another, each phase batched
+  // (one launch per kernel for all its parts); within a phase the parts'
+  // outputs are disjoint, the first phase stores and the others add
+  std::vector<hrt_batch_s*> phases[2];  // [0] forward, [1] adjoint
 };
 
 namespace {
 void free_split(hrt_split_s* sp) {
+  for (auto& ph : sp->phases)
+    for (hrt_batch_s* b : ph) free_batch(b);
   for (hrt_plan_t q : sp->parts) hrt_plan_destroy(q);
   sp->magic = 0;
   delete sp;
@@ -1071,6 +1095,32 @@ hrt_status hrt_split_create(const hrt_desc* desc, int32_t n_t, const int32_t* t_
     }
     sp->parts.push_back(pl);
   }
+  // forward: phase 0 = the last time band of every slowness band (covering
+  // every tau of its rows), phase k = time band k - 1; adjoint: phase 0 =
+  // the first slowness band of every time band, phase k = slowness band k
+  for (int dir = 0; dir < 2; ++dir) {
+    const int nph = dir == 0 ? n_t : n_q;
+    const int per = dir == 0 ? n_q : n_t;
+    for (int k = 0; k < nph; ++k) {
+      auto* b = new hrt_batch_s();
+      b->magic = kBatchMagic;
+      b->device = sp->device;
+      b->owns_plans = false;
+      for (int m = 0; m < per; ++m) {
+        const int part = dir == 0 ? m * n_t + (k == 0 ? n_t - 1 : k - 1) : k * n_t + m;
+        b->plans.push_back(sp->parts[part]);
+      }
+      b->data_off.assign(per + 1, 0);
+      b->radon_off.assign(per + 1, 0);
+      sp->phases[dir].push_back(b);
+      hrt_status s = build_batch_tables(b, std::vector<int>(per, k == 0 ? 0 : 1));
+      if (s != HRT_OK) {
+        const std::string e = g_last_error;
+        free_split(sp);
+        return set_err(s, e);
+      }
+    }
+  }
   *out = sp;
   return HRT_OK;
 }
@@ -1096,21 +1146,11 @@ static hrt_status split_chain(hrt_split_t sp, const float* in, float* out, void*
   DeviceGuard guard(sp->device);
   (void)hipGetLastError();
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int n_t = sp->n_t, n_q = sp->n_q;
-  if (!adjoint) {
-    // the last time band reaches every tau of its slowness rows: it stores,
-    // the earlier bands add
-    for (int iq = 0; iq < n_q; ++iq) {
-      run_chain(sp->parts[iq * n_t + n_t - 1], in, out, st, false, false);
-      for (int it = 0; it < n_t - 1; ++it) run_chain(sp->parts[iq * n_t + it], in, out, st, false, true);
-    }
-  } else {
-    // the time bands cover disjoint data samples; the first slowness band
-    // stores (and zero-fills) them, the others add
-    for (int it = 0; it < n_t; ++it) {
-      run_chain(sp->parts[it], in, out, st, true, false);
-      for (int iq = 1; iq < n_q; ++iq) run_chain(sp->parts[iq * n_t + it], in, out, st, true, true);
-    }
+  const auto& phases = sp->phases[adjoint ? 1 : 0];
+  for (size_t k = 0; k < phases.size(); ++k) {
+    hrt_batch_s* b = phases[k];
+    if (b->plans.size() == 1) run_chain(b->plans[0], in, out, st, adjoint, k > 0);
+    else run_batch(b, in, out, st, adjoint);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, adjoint ? "split adjoint launch" : "split forward launch");
