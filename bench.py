@@ -254,6 +254,39 @@ def batch_c4(torch, np, n=64, reps=10):
     return out
 
 
+def split_c3(torch, np, desc, f, g, gd, reps=20):
+    """The gather cut into parts (Section 4, eq. tsplit; the paper's accuracy
+    runs of Section 5 use one cut in time and one in slowness): time per
+    forward+adjoint, and the forward panels of the plain and the split
+    transform against the GPU direct sum of the same gather (whole panel and
+    the first quarter of tau, where the plain method's errors sit)."""
+    from paper_1604_07651_amd.hrt import Split, split_edges
+    te, qe = split_edges(desc)
+    sp = Split(desc, te, qe)
+    gs = sp.forward(f)
+    fs = sp.adjoint(gs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sp.forward(f, out=gs)
+        sp.adjoint(gs, out=fs)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    q1 = slice(0, desc.ntau // 4)
+
+    def err(x):
+        n = torch.linalg.norm(gd).item()
+        return {"rel_l2": round(torch.linalg.norm(x - gd).item() / n, 4),
+                "first_tau_quarter": round(torch.linalg.norm((x - gd)[:, q1]).item() / n, 4)}
+
+    out = {"t_edges": te, "q_edges": qe, "parts": sp.n_parts,
+           "lattices": [[p["m_theta"], p["m_rho"]] for p in sp.parts],
+           "ms_fwd_adj": round(sec * 1e3, 3), "gathers_per_s": round(1.0 / sec, 1),
+           "vs_direct_sum": {"plain": err(g), "split": err(gs)}}
+    sp.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +297,8 @@ def main():
                     help="skip the trace-interpolation (soft-thresholding) run")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the uneven-batch run")
+    ap.add_argument("--no-split", action="store_true",
+                    help="skip the split-transform run")
     ap.add_argument("--direct-steps", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (reference for "
@@ -380,6 +415,12 @@ def main():
                        "ms_fwd_adj": round(direct_sec * 1e3, 3),
                        "speedup_log_polar": round(direct_sec / sec_per_step, 1)},
     }
+
+    if not args.no_split:
+        log("split transform: one cut in time, one in slowness")
+        plan.forward(f, out=g)
+        plan.direct_forward(f, out=gd)
+        out["split_c3"] = split_c3(torch, np, desc, f, g, gd)
 
     if not args.no_batch:
         log("uneven batch: 64 gathers, one launch per kernel vs one call per gather")
