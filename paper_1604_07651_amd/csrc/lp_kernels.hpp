@@ -176,6 +176,8 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
   for (int i = threadIdx.x; i < nr * W; i += kNtBand) dst[i] = acc[i];
 }
 
+static_assert(kMaxBandRows <= 4, "the row kernels hold at most two row pairs per band");
+
 // Row FFT of one band (item i = band i): the sum of its chunks' partials,
 // fixed point to float (NaN everywhere for a non-finite input), rows
 // (2p, 2p+1) into complex pair p, FFT along the angle, and the k1 < K1 half
@@ -202,23 +204,23 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
   const float inv = scale > 0.0f ? 1.0f / scale : 0.0f;
   const float bad = finite ? 0.0f : __int_as_float(0x7fc00000);
   const int q0 = L.band_chunk[band], q1 = L.band_chunk[band + 1];
-  for (int idx = threadIdx.x; idx < npair * Mt; idx += kNtBand) {
-    const int p = idx / Mt;
-    const int m = idx - p * Mt;
-    const int c = m - G.xw0;
-    float lo = 0.0f, hi = 0.0f;
-    if (c >= 0 && c < W) {
-      // exact integer sums (two's complement, so order does not matter)
-      int a = 0, b = 0;
-      for (int q = q0; q < q1; ++q) {
-        const int* part = G.Hp + static_cast<size_t>(q) * G.R * W;
-        a += part[(2 * p) * W + c];
-        b += part[(2 * p + 1) * W + c];
+  for (int p = 0; p < npair; ++p) {
+    for (int m = threadIdx.x; m < Mt; m += kNtBand) {
+      const int c = m - G.xw0;
+      float lo = 0.0f, hi = 0.0f;
+      if (c >= 0 && c < W) {
+        // exact integer sums (two's complement, so order does not matter)
+        int a = 0, b = 0;
+        for (int q = q0; q < q1; ++q) {
+          const int* part = G.Hp + static_cast<size_t>(q) * G.R * W;
+          a += part[(2 * p) * W + c];
+          b += part[(2 * p + 1) * W + c];
+        }
+        lo = static_cast<float>(a) * inv;
+        hi = static_cast<float>(b) * inv;
       }
-      lo = static_cast<float>(a) * inv;
-      hi = static_cast<float>(b) * inv;
+      lds[p * SP + lpad(m)] = make_float2(lo + bad, hi + bad);
     }
-    lds[p * SP + lpad(m)] = make_float2(lo + bad, hi + bad);
   }
   __syncthreads();
   fft_rows<kNtBand, kInplaceValues, false>(lds, SP, npair,
@@ -226,9 +228,11 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
                                            G.row_group, G.ft, s_tw);
   // two real rows per complex sequence: X1 = (Z[k] + conj Z[-k])/2,
   // X2 = (Z[k] - conj Z[-k])/(2i); keep k1 < K1
+  // npair is 1 or 2 (bands of R = 4 rows, the last one possibly 2)
+  const int psh = npair >> 1;
   for (int idx = threadIdx.x; idx < G.K1 * npair; idx += kNtBand) {
-    const int k = idx / npair;
-    const int p = idx - k * npair;
+    const int k = idx >> psh;
+    const int p = idx & psh;
     const float2 Z = lds[p * SP + lpad(k)];
     const float2 Zm = lds[p * SP + lpad(k == 0 ? 0 : Mt - k)];
     const float4 o = make_float4(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y),
@@ -254,36 +258,32 @@ __global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo one, const DevGeo* 
   const int nc = min(G.col_batch, G.K1 - c0);
   const int Mr = G.Mr, SP = padded_len(G.Mr);
   float2* S = G.S;
-  for (int i = threadIdx.x; i < nc * Mr; i += kNtCol) {
-    const int c = i / Mr;
-    const int n = i - c * Mr;
-    lds[c * SP + lpad(n)] = (n >= G.u0 && n < G.u1) ? S[static_cast<size_t>(c0 + c) * Mr + n]
-                                                    : make_float2(0.f, 0.f);
-  }
+  for (int c = 0; c < nc; ++c)
+    for (int n = threadIdx.x; n < Mr; n += kNtCol)
+      lds[c * SP + lpad(n)] = (n >= G.u0 && n < G.u1) ? S[static_cast<size_t>(c0 + c) * Mr + n]
+                                                      : make_float2(0.f, 0.f);
   __syncthreads();
   float2* cscr = G.col_inplace ? nullptr : lds + SP;
   fft_rows<kNtCol, kInplaceValues, false>(lds, SP, nc, cscr, nc, G.fr, s_tw);
-  for (int i = threadIdx.x; i < nc * Mr; i += kNtCol) {
-    const int c = i / Mr;
-    const int n = i - c * Mr;
-    const int k = (n < Mr / 2) ? n : n - Mr;
-    const int ak = k < 0 ? -k : k;
-    float2 v = make_float2(0.f, 0.f);
-    if (ak < G.K2) {
-      float2 kv = G.K[static_cast<size_t>(c0 + c) * G.K2 + ak];
-      if ((k < 0) != ADJ) kv.y = -kv.y;
-      v = cscale(cmul(lds[c * SP + lpad(n)], kv), G.knorm);
+  for (int c = 0; c < nc; ++c) {
+    for (int n = threadIdx.x; n < Mr; n += kNtCol) {
+      const int k = (n < Mr / 2) ? n : n - Mr;
+      const int ak = k < 0 ? -k : k;
+      float2 v = make_float2(0.f, 0.f);
+      if (ak < G.K2) {
+        float2 kv = G.K[static_cast<size_t>(c0 + c) * G.K2 + ak];
+        if ((k < 0) != ADJ) kv.y = -kv.y;
+        v = cscale(cmul(lds[c * SP + lpad(n)], kv), G.knorm);
+      }
+      lds[c * SP + lpad(n)] = v;
     }
-    lds[c * SP + lpad(n)] = v;
   }
   __syncthreads();
   fft_rows<kNtCol, kInplaceValues, true>(lds, SP, nc, cscr, nc, G.fr, s_tw);
   const int U = G.u1 - G.u0;
-  for (int i = threadIdx.x; i < nc * U; i += kNtCol) {
-    const int c = i / U;
-    const int n = G.u0 + (i - c * U);
-    S[static_cast<size_t>(c0 + c) * Mr + n] = lds[c * SP + lpad(n)];
-  }
+  for (int c = 0; c < nc; ++c)
+    for (int n = G.u0 + threadIdx.x; n < G.u0 + U; n += kNtCol)
+      S[static_cast<size_t>(c0 + c) * Mr + n] = lds[c * SP + lpad(n)];
 }
 
 // Inverse row FFT of one band (item i = band i): Z = X1 + i X2 for rows
@@ -306,9 +306,11 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo one,
   const int Mt = G.Mt, SP = padded_len(G.Mt), W = G.W;
   for (int i = threadIdx.x; i < npair * SP; i += kNtBand) lds[i] = make_float2(0.f, 0.f);
   __syncthreads();
+  // npair is 1 or 2 (bands of R = 4 rows, the last one possibly 2)
+  const int psh = npair >> 1;
   for (int idx = threadIdx.x; idx < G.K1 * npair; idx += kNtBand) {
-    const int k = idx / npair;
-    const int p = idx - k * npair;
+    const int k = idx >> psh;
+    const int p = idx & psh;
     const float4 x = *reinterpret_cast<const float4*>(G.S + static_cast<size_t>(k) * G.Mr + n0 +
                                                       2 * p);
     // X1 = (x.x, x.y), X2 = (x.z, x.w)
@@ -320,12 +322,12 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo one,
                                           fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
                                           G.row_group, G.ft, s_tw);
   float* dst = G.Cr + static_cast<size_t>(n0 - G.u0) * W;
-  for (int idx = threadIdx.x; idx < npair * W; idx += kNtBand) {
-    const int p = idx / W;
-    const int c = idx - p * W;
-    const float2 z = lds[p * SP + lpad(G.xw0 + c)];
-    dst[(2 * p) * W + c] = z.x;
-    dst[(2 * p + 1) * W + c] = z.y;
+  for (int p = 0; p < npair; ++p) {
+    for (int c = threadIdx.x; c < W; c += kNtBand) {
+      const float2 z = lds[p * SP + lpad(G.xw0 + c)];
+      dst[(2 * p) * W + c] = z.x;
+      dst[(2 * p + 1) * W + c] = z.y;
+    }
   }
 }
 
