@@ -121,7 +121,7 @@ __device__ __forceinline__ float spread_scale(const DevGeo& G, float cmax, float
 // LDS: the band's R x W fixed-point rows, then a staging buffer for
 // kSpreadStage entries.  The chunk's entries are read coalesced into the
 // staging buffer; thread s then takes a contiguous segment of it, segments
-// dealt lane-major so that the lanes of a wave work far apart on the lattice.
+// dealt so that the lanes of a wave work far apart on the lattice.
 template <int MODE, bool BATCH>
 __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __restrict__ geos,
                                                     const int2* __restrict__ items,
@@ -145,7 +145,9 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
   __syncthreads();
   if (scale > 0.0f) {
     const int64_t e0 = L.chunk_off[chunk], e1 = L.chunk_off[chunk + 1];
-    const int seg = (threadIdx.x & 63) * (kNtBand / 64) + (threadIdx.x >> 6);
+    // lane l of wave v takes segment (l % 8) * (kNtBand / 8) + 8 v + l / 8:
+    // the eight lane groups of a wave sit an eighth of the stage apart
+    const int seg = (threadIdx.x & 7) * (kNtBand / 8) + (threadIdx.x >> 3);
     for (int64_t c0 = e0; c0 < e1; c0 += kSpreadStage) {
       const int n = static_cast<int>(min(static_cast<int64_t>(kSpreadStage), e1 - c0));
       for (int i = threadIdx.x; i < n; i += kNtBand) stage[i] = L.ent[c0 + i];
