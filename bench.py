@@ -92,6 +92,35 @@ def read_counter_csv(path):
         {k: {c: max(v) for c, v in d.items()} for k, d in out.items()}
 
 
+def summarize_counters(dirs, commands, source_hash):
+    """Shader counters per dispatch of the transform's kernels (rocprofv3
+    --pmc runs, one directory per pass) into profiles/c3_sq_counters.md."""
+    merged = {}
+    for d in dirs:
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            mean, _ = read_counter_csv(path)
+            for k, cs in mean.items():
+                merged.setdefault(k, {}).update(cs)
+    names = sorted({c for cs in merged.values() for c in cs})
+    md = os.path.join(ROOT, "profiles", "c3_sq_counters.md")
+    with open(md, "w") as fh:
+        fh.write("# Shader counters per dispatch, C3 forward+adjoint (2048x1024 -> 2048x1024)\n\n")
+        fh.write("Commands (run from the repository root on one MI355X):\n\n")
+        for c in commands:
+            fh.write(f"    {c}\n")
+        fh.write("\nSums over the whole chip per dispatch: SQ_INSTS_* count wave instructions, "
+                 "SQ_*_CYCLES and SQ_WAIT_* count wave (or SIMD) cycles, "
+                 "SQ_LDS_BANK_CONFLICT the cycles LDS spent on bank conflicts.\n\n")
+        fh.write("| kernel | " + " | ".join(names) + " |\n")
+        fh.write("|---|" + "---|" * len(names) + "\n")
+        for k in STAGE_KERNELS:
+            if k in merged:
+                fh.write(f"| {k} | " + " | ".join(f"{merged[k].get(c, float('nan')):.4g}"
+                                                  for c in names) + " |\n")
+        fh.write(f"\nKernel source hash: {source_hash}\n")
+    print(f"wrote {md}")
+
+
 def summarize_profiles(trace_dir, fetch_dir, write_dir, commands, source_hash):
     """Turn rocprofv3 outputs (CSV) into the committed text summaries;
     `source_hash` is the kernel_source_hash the measured runs printed."""
@@ -287,6 +316,47 @@ def split_c3(torch, np, desc, f, g, gd, reps=20):
     return out
 
 
+# the paper's per-iteration GPU times on N x N gathers (GTX 970, float32,
+# device resident; Section 5, table timesiters), seconds: context only
+PAPER_ITER_S = {512: (1.9e-3, 2.3e-3), 1024: (7.4e-3, 8.7e-3), 2048: (2.9e-2, 3.2e-2),
+                4096: (1.1e-1, 1.3e-1)}
+
+
+def sweep_s1(torch, np, sizes=(512, 1024, 2048, 4096), reps=20):
+    """Forward and adjoint times on square gathers (Nt = Nx = Ntau = Nq = N,
+    30 Ricker events), beside the paper's per-iteration times for the same
+    sizes on its own hardware and gather (context, not a target)."""
+    import synth
+    from paper_1604_07651_amd.hrt import Plan
+    out = []
+    for n in sizes:
+        desc = synth.s1_desc(n)
+        f = torch.from_numpy(synth.s1_gather(n, dtype=np.float32)).cuda()
+        t0 = time.perf_counter()
+        plan = Plan(desc)
+        plan_s = time.perf_counter() - t0
+        g = plan.forward(f)
+        fa = plan.adjoint(g)
+        row = {"n": n, "lattice": [plan.info["m_theta"], plan.info["m_rho"]],
+               "plan_s": round(plan_s, 3)}
+        for name, fn in (("fwd", lambda: plan.forward(f, out=g)),
+                         ("adj", lambda: plan.adjoint(g, out=fa))):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            row[f"{name}_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 4)
+        pf, pa = PAPER_ITER_S[n]
+        row["paper_gtx970_fwd_ms"] = pf * 1e3
+        row["paper_gtx970_adj_ms"] = pa * 1e3
+        out.append(row)
+        plan.close()
+        del f, g, fa
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +369,8 @@ def main():
                     help="skip the uneven-batch run")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the split-transform run")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the N x N size sweep")
     ap.add_argument("--direct-steps", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 256 MiB device copy (reference for "
@@ -306,12 +378,18 @@ def main():
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
                     help="write profiles/ summaries from rocprofv3 CSV output "
                          "directories (no GPU needed)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="write profiles/c3_sq_counters.md from rocprofv3 --pmc CSV "
+                         "directories (no GPU needed)")
     ap.add_argument("--profile-commands", nargs="*", default=[])
     ap.add_argument("--profile-hash", default="",
                     help="kernel_source_hash printed by the profiled runs")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(*args.summarize_profiles, args.profile_commands, args.profile_hash)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.profile_commands, args.profile_hash)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the transform of a gather runs on "
@@ -421,6 +499,10 @@ def main():
         plan.forward(f, out=g)
         plan.direct_forward(f, out=gd)
         out["split_c3"] = split_c3(torch, np, desc, f, g, gd)
+
+    if not args.no_sweep:
+        log("size sweep: N x N gathers, N = 512 ... 4096")
+        out["sweep_s1"] = sweep_s1(torch, np)
 
     if not args.no_batch:
         log("uneven batch: 64 gathers, one launch per kernel vs one call per gather")

@@ -8,8 +8,9 @@ code of the method.
 from .gathers import (GridDesc, CONFIGS, config_desc, ricker, ricker_gather,
                       config_gather, gaussian_sy_gather, trace_mask,
                       batch_descs, batch_gathers, random_pair, c5_batch,
-                      demultiple_gather)
+                      demultiple_gather, s1_desc, s1_gather)
 
 __all__ = ["GridDesc", "CONFIGS", "config_desc", "ricker", "ricker_gather",
            "config_gather", "gaussian_sy_gather", "trace_mask", "batch_descs",
-           "batch_gathers", "random_pair", "c5_batch", "demultiple_gather"]
+           "batch_gathers", "random_pair", "c5_batch", "demultiple_gather",
+           "s1_desc", "s1_gather"]

@@ -107,6 +107,19 @@ def ricker_gather(desc: GridDesc, events: int, freq: float, seed: int,
     return f.astype(dtype)
 
 
+def s1_desc(n: int) -> GridDesc:
+    """Square grids of the size sweep beside the paper's timing tables
+    (Nt = Nx = Ntau = Nq = n): t over about 4 s, offsets 0..4 km, slownesses
+    for 1.5..4 km/s."""
+    return GridDesc(nt=n, nx=n, dt=4.0 / n, x0=0.0, dx=4.0 / (n - 1), ntau=n, nq=n,
+                    tau0=0.0, dtau=4.0 / n, q0=Q_MIN, dq=(Q_MAX - Q_MIN) / (n - 1))
+
+
+def s1_gather(n: int, dtype=np.float64) -> np.ndarray:
+    """30 Ricker events of 25 Hz on s1_desc(n) (seed 6)."""
+    return ricker_gather(s1_desc(n), 30, 25.0, 6, dtype=dtype)
+
+
 def config_gather(name: str, dtype=np.float64) -> np.ndarray:
     c = CONFIGS[name]
     return ricker_gather(c["desc"], c["events"], c["freq"], c["seed"],
