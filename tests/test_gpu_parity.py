@@ -27,6 +27,9 @@ SMALL = {
                              nq=61, tau0=0.05, dtau=0.0045, q0=0.22, dq=0.0075,
                              oversample=2.0),
     "c2": synth.config_desc("c2"),
+    # q0 = 0: the trapezoid keeps every sample
+    "q0zero": synth.GridDesc(nt=64, nx=48, dt=0.01, x0=0.0, dx=0.03, ntau=60, nq=40,
+                             tau0=0.0, dtau=0.01, q0=0.0, dq=0.008),
     # more traces and slownesses than a band workgroup has threads
     "wide": synth.GridDesc(nt=96, nx=1500, dt=0.004, x0=0.0, dx=4.0 / 1499, ntau=80,
                            nq=1100, tau0=0.0, dtau=0.0048, q0=0.25,
@@ -69,7 +72,7 @@ def test_kernel_multiplier_matches_oracle(name):
     assert np.abs(K - ref).max() <= 2e-7 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("name", ["c1", "odd", "tiny", "ragged", "wide", "c2"])
+@pytest.mark.parametrize("name", ["c1", "odd", "tiny", "ragged", "q0zero", "wide", "c2"])
 @pytest.mark.parametrize("kind", ["random", "ricker"])
 def test_forward_and_adjoint_parity(name, kind):
     desc, plan, ora = setup(name)
@@ -125,6 +128,24 @@ def test_full_size_parity(name):
     fa = plan.adjoint(g)
     torch.cuda.synchronize()
     compare(fa.cpu().numpy(), ora.adjoint(g_np), f"adjoint {name}")
+
+
+def test_non_finite_input_gives_nan_everywhere():
+    """One NaN or inf in the input makes the whole output NaN (the spread's
+    fixed-point scale cannot be formed), in both directions."""
+    desc, plan, ora = setup("c1")
+    f, g = synth.random_pair(desc, 8)
+    print("[gpu] non-finite inputs", flush=True)
+    for bad in (float("nan"), float("inf")):
+        F = to_gpu(f)
+        F[3, 100] = bad
+        assert torch.isnan(plan.forward(F)).all()
+        G = to_gpu(g)
+        G[5, 7] = bad
+        out = plan.adjoint(G)
+        assert torch.isnan(out[torch.from_numpy(ora.geo.keep).cuda()]).all()
+    # a finite input afterwards is unaffected
+    compare(plan.forward(to_gpu(f)).cpu().numpy(), ora.forward(f), "forward after NaN")
 
 
 def test_zero_input_gives_zero_output():
