@@ -32,6 +32,7 @@ struct DevList {
 struct DevGeo {
   int nt, nx, ntau, nq;
   int Mt, Mr, K1, K2, u0, u1, R, nbands;
+  int row_rows, row_sub_shift;  // rows of a row-FFT item, log2 items per band
   int xw0, W;         // angle columns [xw0, xw0 + W) that points can touch
   int x_frac_bits;    // fraction bits of the angle coordinate of a point entry
   // row FFTs: sequences per group, byte offset of the LDS scratch (-1: in

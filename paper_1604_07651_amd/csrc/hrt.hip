@@ -129,6 +129,17 @@ std::vector<float2> twiddles(int n) {
   return t;
 }
 
+// Row-FFT items of a plan: band b's rows from s * row_rows on are item
+// (b << row_sub_shift) + s, for every s whose rows exist.
+std::vector<int> row_items(const Geometry& g) {
+  std::vector<int> out;
+  for (int b = 0; b < g.nbands; ++b) {
+    const int rows = std::min(g.R, g.u1 - (g.u0 + b * g.R));
+    for (int s = 0; s * g.row_rows < rows; ++s) out.push_back((b << g.row_sub_shift) + s);
+  }
+  return out;
+}
+
 template <typename T>
 hrt_status dev_alloc(T** p, size_t count, size_t& total) {
   const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
@@ -446,6 +457,7 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
   G.nt = g.d.nt; G.nx = g.d.nx;
   G.Mt = g.Mt; G.Mr = g.Mr; G.K1 = g.K1; G.K2 = g.K2; G.u0 = g.u0; G.u1 = g.u1;
   G.R = g.R; G.nbands = g.nbands;
+  G.row_rows = g.row_rows; G.row_sub_shift = g.row_sub_shift;
   G.xw0 = g.xw0; G.W = g.W; G.x_frac_bits = g.x_frac_bits;
   G.row_group = g.row_group; G.row_scratch = g.row_scratch;
   G.col_inplace = g.inplace_col ? 1 : 0;
@@ -476,7 +488,7 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
     for (int c = 0; c < p->nchunks[kDataSpread]; ++c) it[kItSpreadData].push_back(make_int2(0, c));
     for (int c = 0; c < p->nchunks[kRadonSpread]; ++c)
       it[kItSpreadRadon].push_back(make_int2(0, c));
-    for (int b = 0; b < g.nbands; ++b) it[kItBands].push_back(make_int2(0, b));
+    for (int r : row_items(g)) it[kItBands].push_back(make_int2(0, r));
     for (int c = 0; c < (g.K1 + g.col_batch - 1) / g.col_batch; ++c)
       it[kItCols].push_back(make_int2(0, c));
     for (int c = 0; c < p->nchunks[kRadonOwn]; ++c) it[kItGatherRadon].push_back(make_int2(0, c));
@@ -868,7 +880,7 @@ hrt_status build_batch_tables(hrt_batch_s* b, const std::vector<int>& accumulate
     for (int k = 0; k < pl->nchunks[kDataSpread]; ++k) it[kItSpreadData].push_back(make_int2(i, k));
     for (int k = 0; k < pl->nchunks[kRadonSpread]; ++k)
       it[kItSpreadRadon].push_back(make_int2(i, k));
-    for (int k = 0; k < pl->g.nbands; ++k) it[kItBands].push_back(make_int2(i, k));
+    for (int r : row_items(pl->g)) it[kItBands].push_back(make_int2(i, r));
     for (int k = 0; k < pl->nitems[kItCols]; ++k) it[kItCols].push_back(make_int2(i, k));
     for (int k = 0; k < pl->nchunks[kRadonOwn]; ++k) it[kItGatherRadon].push_back(make_int2(i, k));
     for (int k = 0; k < pl->nchunks[kDataOwn]; ++k) it[kItGatherData].push_back(make_int2(i, k));

@@ -178,9 +178,19 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
   for (int i = threadIdx.x; i < nr * W; i += kNtBand) dst[i] = acc[i];
 }
 
-static_assert(kMaxBandRows <= 4, "the row kernels hold at most two row pairs per band");
+static_assert(kMaxBandRows >= 2 && (kMaxBandRows & (kMaxBandRows - 1)) == 0,
+              "band heights are powers of two");
 
-// Row FFT of one band (item i = band i): the sum of its chunks' partials,
+// log2 of a band's row-pair count, for pair counts 1, 2, 4, ... (the last
+// band of a plan may hold fewer rows; its pair count is rounded up to a
+// power of two and the missing pairs are skipped)
+__device__ __forceinline__ int pair_shift(int npair) {
+  return 31 - __clz(npair) + ((npair & (npair - 1)) ? 1 : 0);
+}
+
+// Row FFT of row_rows rows of a band (item i: band i >> row_sub_shift, the
+// rows from (i mod 2^row_sub_shift) * row_rows on): the sum of the band's
+// chunks' partials of those rows,
 // fixed point to float (NaN everywhere for a non-finite input), rows
 // (2p, 2p+1) into complex pair p, FFT along the angle, and the k1 < K1 half
 // spectrum of both rows to S.  Dynamic LDS: the pairs, then the FFT scratch
@@ -195,10 +205,11 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
   const Work w = work_item<BATCH>(one, geos, items);
   const DevGeo& G = w.G;
   const DevList& L = G.lists[MODE == 0 ? kDataSpread : kRadonSpread];
-  const int band = w.i;
+  const int band = w.i >> G.row_sub_shift;
+  const int r0 = (w.i & ((1 << G.row_sub_shift) - 1)) * G.row_rows;  // first row in the band
   load_twiddles<kNtBand>(s_tw, G.tw_t, G.Mt);
-  const int n0 = G.u0 + band * G.R;
-  const int nr = min(G.R, G.u1 - n0);
+  const int n0 = G.u0 + band * G.R + r0;
+  const int nr = min(G.row_rows, G.u1 - n0);
   const int npair = nr >> 1;
   const int Mt = G.Mt, W = G.W, SP = padded_len(G.Mt);
   bool finite;
@@ -214,7 +225,7 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
         // exact integer sums (two's complement, so order does not matter)
         int a = 0, b = 0;
         for (int q = q0; q < q1; ++q) {
-          const int* part = G.Hp + static_cast<size_t>(q) * G.R * W;
+          const int* part = G.Hp + (static_cast<size_t>(q) * G.R + r0) * W;
           a += part[(2 * p) * W + c];
           b += part[(2 * p + 1) * W + c];
         }
@@ -230,11 +241,11 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
                                            G.row_group, G.ft, s_tw);
   // two real rows per complex sequence: X1 = (Z[k] + conj Z[-k])/2,
   // X2 = (Z[k] - conj Z[-k])/(2i); keep k1 < K1
-  // npair is 1 or 2 (bands of R = 4 rows, the last one possibly 2)
-  const int psh = npair >> 1;
-  for (int idx = threadIdx.x; idx < G.K1 * npair; idx += kNtBand) {
+  const int psh = pair_shift(npair);
+  for (int idx = threadIdx.x; idx < (G.K1 << psh); idx += kNtBand) {
     const int k = idx >> psh;
-    const int p = idx & psh;
+    const int p = idx & ((1 << psh) - 1);
+    if (p >= npair) continue;
     const float2 Z = lds[p * SP + lpad(k)];
     const float2 Zm = lds[p * SP + lpad(k == 0 ? 0 : Mt - k)];
     const float4 o = make_float4(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y),
@@ -288,7 +299,8 @@ __global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo one, const DevGeo* 
       S[static_cast<size_t>(c0 + c) * Mr + n] = lds[c * SP + lpad(n)];
 }
 
-// Inverse row FFT of one band (item i = band i): Z = X1 + i X2 for rows
+// Inverse row FFT of row_rows rows of a band (item i as in k_rowfft):
+// Z = X1 + i X2 for rows
 // (2p, 2p+1) with the Hermitian completion Z[-k], inverse FFT along the
 // angle, real rows to Cr (window columns only).  Dynamic LDS: the pairs,
 // then the FFT scratch.
@@ -300,19 +312,20 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo one,
   __shared__ float2 s_tw[kTwLds];
   const Work w = work_item<BATCH>(one, geos, items);
   const DevGeo& G = w.G;
-  const int band = w.i;
+  const int band = w.i >> G.row_sub_shift;
+  const int r0 = (w.i & ((1 << G.row_sub_shift) - 1)) * G.row_rows;  // first row in the band
   load_twiddles<kNtBand>(s_tw, G.tw_t, G.Mt);
-  const int n0 = G.u0 + band * G.R;
-  const int nr = min(G.R, G.u1 - n0);
+  const int n0 = G.u0 + band * G.R + r0;
+  const int nr = min(G.row_rows, G.u1 - n0);
   const int npair = nr >> 1;
   const int Mt = G.Mt, SP = padded_len(G.Mt), W = G.W;
   for (int i = threadIdx.x; i < npair * SP; i += kNtBand) lds[i] = make_float2(0.f, 0.f);
   __syncthreads();
-  // npair is 1 or 2 (bands of R = 4 rows, the last one possibly 2)
-  const int psh = npair >> 1;
-  for (int idx = threadIdx.x; idx < G.K1 * npair; idx += kNtBand) {
+  const int psh = pair_shift(npair);
+  for (int idx = threadIdx.x; idx < (G.K1 << psh); idx += kNtBand) {
     const int k = idx >> psh;
-    const int p = idx & psh;
+    const int p = idx & ((1 << psh) - 1);
+    if (p >= npair) continue;
     const float4 x = *reinterpret_cast<const float4*>(G.S + static_cast<size_t>(k) * G.Mr + n0 +
                                                       2 * p);
     // X1 = (x.x, x.y), X2 = (x.z, x.w)

@@ -420,21 +420,30 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   };
   auto layout = [&](int R, bool commit) {
     const int64_t spread = static_cast<int64_t>(R) * g.W * 4 + int64_t{kSpreadStage} * 16;
-    const int grp = inplace_group(R / 2);
-    const int64_t pairs = (R / 2) * seq;
+    const int rr = std::min(R, kRowRows);  // rows of a row-FFT item
+    const int grp = inplace_group(rr / 2);
+    const int64_t pairs = (rr / 2) * seq;
     const int64_t row = pairs + (grp ? 0 : pairs);
     const int64_t gather = static_cast<int64_t>(R + 3) * g.W * 4;
     if (commit) {
       g.spread_bytes = static_cast<int>(spread);
       g.row_bytes = static_cast<int>(row);
       g.gather_bytes = static_cast<int>(gather);
-      g.row_group = grp ? grp : R / 2;
+      g.row_group = grp ? grp : rr / 2;
       g.row_scratch = grp ? -1 : static_cast<int>(pairs);
+      g.row_rows = rr;
+      g.row_sub_shift = 0;
+      while ((rr << g.row_sub_shift) < R) ++g.row_sub_shift;
     }
     return std::max(std::max(spread, row), gather);
   };
+  // band heights 2, 4, 8, ...: a band holds a power-of-two number of row
+  // pairs, and the last band an even number of rows not above it
   g.R = kMaxBandRows;
-  while (g.R > 2 && layout(g.R, false) > lds_bytes) g.R -= 2;
+  while (g.R > 4 && static_cast<int64_t>(g.R) * g.W * 4 + int64_t{kSpreadStage} * 16 >
+                        kBandLdsPreferred)
+    g.R /= 2;
+  while (g.R > 2 && layout(g.R, false) > lds_bytes) g.R /= 2;
   if (layout(g.R, false) > lds_bytes)
     return fail(err, HRT_ERR_UNSUPPORTED, "angle axis too long for the LDS row bands");
   layout(g.R, true);

@@ -15,8 +15,14 @@ namespace hrt {
 // FFT passes: at most 8, radices from this list, largest first.
 constexpr int kMaxPasses = 8;
 constexpr int kFftRadices[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
-// Tallest row band of the spread / gather kernels.
-constexpr int kMaxBandRows = 4;
+// Tallest row band of the spread / gather kernels, and the rows one
+// workgroup of the row FFT kernels takes (a band of R rows is R / kRowRows
+// row items, or one item when it is lower).
+constexpr int kMaxBandRows = 8;
+constexpr int kRowRows = 4;
+// Bands taller than 4 rows are taken only while a spread workgroup's LDS
+// stays within this, so that several workgroups share a CU.
+constexpr int kBandLdsPreferred = 64 * 1024;
 // Static LDS of the band kernels (twiddles, reduction slots), rounded up.
 constexpr int kBandStaticLds = 4096;
 // Threads of the band kernels and of the column kernel.
@@ -27,8 +33,8 @@ constexpr int kInplaceValues = 16;
 // Point lists are cut into chunks of at most these many entries (spread:
 // each chunk writes one partial of its band's rows; gather: one workgroup),
 // and the spread stages kSpreadStage entries at a time in LDS.
-constexpr int kSpreadChunk = 8192;
-constexpr int kGatherChunk = 2048;
+constexpr int kSpreadChunk = 4096;
+constexpr int kGatherChunk = 4096;
 constexpr int kSpreadStage = 1024;
 // Fraction bits of the log-radius coordinate in a point entry (the integer
 // part, the row relative to the band's first tap row, needs 3 bits).
@@ -107,7 +113,9 @@ struct Geometry {
   // rho = (n - crho) drho; all used nodes fall inside the array.
   int ctheta = 0, crho = 0;
   int u0 = 0, u1 = 0;         // lattice rows touched by any point [u0, u1)
-  int R = 0, nbands = 0;      // row band height (even) and band count
+  int R = 0, nbands = 0;      // row band height (a power of two) and band count
+  int row_rows = 0;           // rows of a row-FFT item: min(R, kRowRows)
+  int row_sub_shift = 0;      // log2 of the row items per band
   // row FFTs (forward and inverse): in place `row_group` sequences at a
   // time, or through an LDS scratch of `row_group` sequences at byte offset
   // row_scratch (-1 when in place); the column FFT in place or not
