@@ -33,7 +33,7 @@ constexpr int kInplaceValues = 16;
 // Point lists are cut into chunks of at most these many entries (spread:
 // each chunk writes one partial of its band's rows; gather: one workgroup),
 // and the spread stages kSpreadStage entries at a time in LDS.
-constexpr int kSpreadChunk = 4096;
+constexpr int kSpreadChunk = 5120;
 constexpr int kGatherChunk = 4096;
 constexpr int kSpreadStage = 1024;
 // Fraction bits of the log-radius coordinate in a point entry (the integer
