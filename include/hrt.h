@@ -201,6 +201,26 @@ hrt_status hrt_batch_adjoint(hrt_batch_t batch, const float* g_packed, float* f_
 hrt_status hrt_batch_plan(hrt_batch_t batch, int32_t i, hrt_plan_t* out);
 void hrt_batch_destroy(hrt_batch_t batch);
 
+/* Soft-thresholding iterations (Section 3, eq. itersmd, as
+ * hrt_ista_iterate) for every gather of a batch at once: per iteration one
+ * batched adjoint, the residual over all packed samples, one batched
+ * forward and the update g_i <- S_{c2_i mu_i}(g_i + c2_i d_i), each gather
+ * with its own step c2[i] > 0 and weight mu[i] >= 0 (host arrays of n
+ * floats).  f, mask (NULL: every sample recorded) and work_data are packed
+ * data arrays, g and work_radon packed Radon arrays (hrt_batch_offsets);
+ * they must not overlap.  hrt_batch_ista_iterate enqueues (after a small
+ * host-to-device copy of the per-gather parameters into the batch);
+ * hrt_batch_ista_graph_create captures the same work into a HIP graph that
+ * keeps its own copy of the parameters (launch with hrt_graph_launch). */
+hrt_status hrt_batch_ista_iterate(hrt_batch_t batch, const float* f, const float* mask,
+                                  float* g, float* work_data, float* work_radon,
+                                  int32_t iters, const float* c2, const float* mu,
+                                  void* stream);
+hrt_status hrt_batch_ista_graph_create(hrt_batch_t batch, const float* f, const float* mask,
+                                       float* g, float* work_data, float* work_radon,
+                                       int32_t iters, const float* c2, const float* mu,
+                                       hrt_graph_t* out);
+
 /* Splitting into parts (Section 4, eq. tsplit: the integral over t cut at
  * intermediate times, so that each part gets the log-polar lattice its own
  * samples need; Section 5 applies the same to the slowness range).  The

@@ -66,6 +66,14 @@ SIGNATURES = [
     ("hrt_batch_adjoint", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("hrt_batch_plan", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     ("hrt_batch_destroy", None, [C.c_void_p]),
+    ("hrt_batch_ista_iterate", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_int32,
+                                         C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                         C.c_void_p]),
+    ("hrt_batch_ista_graph_create", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                              C.c_void_p, C.c_void_p, C.c_int32,
+                                              C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                              C.POINTER(C.c_void_p)]),
     ("hrt_split_describe", C.c_int, [C.POINTER(HrtDesc), C.c_int32, C.POINTER(C.c_int32),
                                      C.c_int32, C.POINTER(C.c_int32), C.c_int32,
                                      C.POINTER(HrtDesc), C.POINTER(C.c_int32),

@@ -668,7 +668,42 @@ struct hrt_graph_s {
   uint64_t magic;
   int device;
   hipGraphExec_t exec;
+  void* owned;  // device memory the graph's kernels read (freed with it)
 };
+
+// Captures what `enqueue` launches on a private stream of `device` into an
+// executable graph; the graph takes ownership of `owned` (also on failure).
+extern "C++" template <class EnqueueF>
+static hrt_status capture_graph(int device, EnqueueF enqueue, void* owned, hrt_graph_t* out) {
+  DeviceGuard guard(device);
+  auto drop = [&](hrt_status s) {
+    if (owned) (void)hipFree(owned);
+    return s;
+  };
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return drop(hip_err(e, "hipStreamCreate"));
+  hipGraph_t graph = nullptr;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return drop(hip_err(e, "hipStreamBeginCapture"));
+  }
+  hrt_status s = enqueue(cs);
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (s != HRT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return drop(s);
+  }
+  if (e != hipSuccess) return drop(hip_err(e, "hipStreamEndCapture"));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return drop(hip_err(e, "hipGraphInstantiate"));
+  *out = new hrt_graph_s{kGraphMagic, device, exec, owned};
+  return HRT_OK;
+}
 
 hrt_status hrt_ista_graph_create(hrt_plan_t p, const float* f, const float* mask, float* g,
                                  float* work_data, float* work_radon, int32_t iters, float c2,
@@ -678,30 +713,12 @@ hrt_status hrt_ista_graph_create(hrt_plan_t p, const float* f, const float* mask
   if (!out) return set_err(HRT_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
   if (!p->prof_ev.empty()) return set_err(HRT_ERR_INVALID_ARG, "profiling is active");
-  DeviceGuard guard(p->device);
-  hipStream_t cs = nullptr;
-  HRT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
-  hipGraph_t graph = nullptr;
-  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) {
-    (void)hipStreamDestroy(cs);
-    return hip_err(e, "hipStreamBeginCapture");
-  }
-  s = hrt_ista_iterate(p, f, mask, g, work_data, work_radon, iters, c2, mu, cs);
-  e = hipStreamEndCapture(cs, &graph);
-  (void)hipStreamDestroy(cs);
-  if (s != HRT_OK) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return s;
-  }
-  if (e != hipSuccess) return hip_err(e, "hipStreamEndCapture");
-  hipGraphExec_t exec = nullptr;
-  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) return hip_err(e, "hipGraphInstantiate");
-  auto* gr = new hrt_graph_s{kGraphMagic, p->device, exec};
-  *out = gr;
-  return HRT_OK;
+  return capture_graph(
+      p->device,
+      [&](hipStream_t cs) {
+        return hrt_ista_iterate(p, f, mask, g, work_data, work_radon, iters, c2, mu, cs);
+      },
+      nullptr, out);
 }
 
 hrt_status hrt_graph_launch(hrt_graph_t gr, void* stream) {
@@ -716,6 +733,7 @@ void hrt_graph_destroy(hrt_graph_t gr) {
   DeviceGuard guard(gr->device);
   (void)hipDeviceSynchronize();
   (void)hipGraphExecDestroy(gr->exec);
+  if (gr->owned) (void)hipFree(gr->owned);
   gr->magic = 0;
   delete gr;
 }
@@ -837,6 +855,8 @@ struct hrt_batch_s {
   std::vector<hrt_plan_t> plans;
   std::vector<int64_t> data_off, radon_off;  // n + 1 each, in floats
   DevGeo* geos = nullptr;                    // one descriptor per gather
+  int64_t* radon_off_dev = nullptr;          // radon_off on the device
+  float2* ista_par = nullptr;                // (c^2, c^2 mu / 2) per gather
   int2* items[kItemSets] = {};
   int nitems[kItemSets] = {};
   int spread_bytes = 0, row_bytes = 0, col_bytes = 0, gather_bytes = 0;
@@ -845,6 +865,8 @@ struct hrt_batch_s {
 namespace {
 void free_batch(hrt_batch_s* b) {
   if (b->geos) (void)hipFree(b->geos);
+  if (b->radon_off_dev) (void)hipFree(b->radon_off_dev);
+  if (b->ista_par) (void)hipFree(b->ista_par);
   for (int2* q : b->items)
     if (q) (void)hipFree(q);
   if (b->owns_plans)
@@ -932,6 +954,13 @@ hrt_status hrt_batch_create(const hrt_desc* descs, int32_t n, hrt_batch_t* out) 
     b->radon_off[i + 1] = b->radon_off[i] + static_cast<int64_t>(g.d.nq) * g.d.ntau;
   }
   hrt_status s = build_batch_tables(b, std::vector<int>(n, 0));
+  if (s == HRT_OK) {
+    DeviceGuard guard(b->device);
+    size_t total = 0;
+    if ((s = dev_alloc(&b->radon_off_dev, b->radon_off.size(), total)) == HRT_OK &&
+        (s = upload(b->radon_off_dev, b->radon_off)) == HRT_OK)
+      s = dev_alloc(&b->ista_par, static_cast<size_t>(n), total);
+  }
   if (s != HRT_OK) {
     free_batch(b);
     return s;
@@ -1010,6 +1039,95 @@ hrt_status hrt_batch_forward(hrt_batch_t b, const float* f, float* g, void* stre
 
 hrt_status hrt_batch_adjoint(hrt_batch_t b, const float* g, float* f, void* stream) {
   return batch_chain(b, g, f, stream, true);
+}
+
+// Soft-thresholding iterations over a batch (arguments checked by the
+// caller): per iteration the batched adjoint, the residual over all packed
+// samples, the batched forward, the per-gather update with par[b].
+static hrt_status batch_ista_enqueue(hrt_batch_t b, const float* f, const float* mask, float* g,
+                                     float* work_data, float* work_radon, int32_t iters,
+                                     const float2* par, hipStream_t st) {
+  const int64_t n_data = b->data_off.back();
+  const int n = static_cast<int>(b->plans.size());
+  for (int it = 0; it < iters; ++it) {
+    run_batch(b, g, work_data, st, true);
+    k_residual<<<vec_blocks(n_data), kVecThreads, 0, st>>>(f, mask, work_data, n_data);
+    run_batch(b, work_data, work_radon, st, false);
+    k_soft_update_batch<<<vec_blocks(b->radon_off.back()), kVecThreads, 0, st>>>(
+        g, work_radon, par, b->radon_off_dev, n);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(e, "batch ista launch");
+  return HRT_OK;
+}
+
+// Validates the batch ISTA arguments and packs (c2_i, c2_i mu_i / 2).
+static hrt_status batch_ista_args(hrt_batch_t b, const float* f, const float* mask, float* g,
+                                  float* work_data, float* work_radon, int32_t iters,
+                                  const float* c2, const float* mu, std::vector<float2>& par) {
+  hrt_status s = check_batch(b);
+  if (s != HRT_OK) return s;
+  if (!f || !g || !work_data || !work_radon || !c2 || !mu)
+    return set_err(HRT_ERR_INVALID_ARG, "null array");
+  if (iters < 0) return set_err(HRT_ERR_INVALID_ARG, "need iters >= 0");
+  const size_t n = b->plans.size();
+  par.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (!(c2[i] > 0.0f) || !(mu[i] >= 0.0f))
+      return set_err(HRT_ERR_INVALID_ARG, "need c2 > 0 and mu >= 0 for every gather");
+    par[i] = make_float2(c2[i], 0.5f * c2[i] * mu[i]);
+  }
+  const size_t nd = static_cast<size_t>(b->data_off.back()) * sizeof(float);
+  const size_t nr = static_cast<size_t>(b->radon_off.back()) * sizeof(float);
+  if (overlaps(g, nr, work_radon, nr) || overlaps(g, nr, work_data, nd) ||
+      overlaps(g, nr, f, nd) || overlaps(work_data, nd, work_radon, nr) ||
+      overlaps(work_data, nd, f, nd) || overlaps(work_radon, nr, f, nd) ||
+      (mask && (overlaps(mask, nd, work_data, nd) || overlaps(mask, nd, g, nr) ||
+                overlaps(mask, nd, work_radon, nr))))
+    return set_err(HRT_ERR_INVALID_ARG, "arrays overlap");
+  return HRT_OK;
+}
+
+hrt_status hrt_batch_ista_iterate(hrt_batch_t b, const float* f, const float* mask, float* g,
+                                  float* work_data, float* work_radon, int32_t iters,
+                                  const float* c2, const float* mu, void* stream) {
+  std::vector<float2> par;
+  hrt_status s = batch_ista_args(b, f, mask, g, work_data, work_radon, iters, c2, mu, par);
+  if (s != HRT_OK) return s;
+  DeviceGuard guard(b->device);
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HRT_HIP(hipMemcpyAsync(b->ista_par, par.data(), par.size() * sizeof(float2),
+                         hipMemcpyHostToDevice, st),
+          "upload ista parameters");
+  return batch_ista_enqueue(b, f, mask, g, work_data, work_radon, iters, b->ista_par, st);
+}
+
+hrt_status hrt_batch_ista_graph_create(hrt_batch_t b, const float* f, const float* mask,
+                                       float* g, float* work_data, float* work_radon,
+                                       int32_t iters, const float* c2, const float* mu,
+                                       hrt_graph_t* out) {
+  if (!out) return set_err(HRT_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  std::vector<float2> par;
+  hrt_status s = batch_ista_args(b, f, mask, g, work_data, work_radon, iters, c2, mu, par);
+  if (s != HRT_OK) return s;
+  DeviceGuard guard(b->device);
+  // the graph's own copy of the parameters, so later calls cannot change it
+  float2* gpar = nullptr;
+  size_t total = 0;
+  if ((s = dev_alloc(&gpar, par.size(), total)) != HRT_OK) return s;
+  hipError_t e = hipMemcpy(gpar, par.data(), par.size() * sizeof(float2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(gpar);
+    return hip_err(e, "upload ista parameters");
+  }
+  return capture_graph(
+      b->device,
+      [&](hipStream_t cs) {
+        return batch_ista_enqueue(b, f, mask, g, work_data, work_radon, iters, gpar, cs);
+      },
+      gpar, out);
 }
 
 void hrt_batch_destroy(hrt_batch_t b) {

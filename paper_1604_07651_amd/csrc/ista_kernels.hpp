@@ -42,6 +42,28 @@ __global__ __launch_bounds__(kVecThreads) void k_soft_update(float* __restrict__
   }
 }
 
+// The same update over the packed Radon panels of a batch: element i
+// belongs to gather b with off[b] <= i < off[b+1] (found by bisection over
+// the n + 1 offsets) and takes that gather's (c^2, c^2 mu / 2) = par[b].
+__global__ __launch_bounds__(kVecThreads) void k_soft_update_batch(
+    float* __restrict__ g, const float* __restrict__ d, const float2* __restrict__ par,
+    const int64_t* __restrict__ off, int n) {
+  const int64_t total = off[n];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += stride) {
+    int lo = 0, hi = n;  // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    const float2 p = par[lo];
+    const float v = fmaf(p.x, d[i], g[i]);
+    g[i] = v >= p.y ? v - p.y : (v <= -p.y ? v + p.y : 0.0f);
+  }
+}
+
 // kDotBlocks partial sums of a[i] * b[i] accumulated in float64.
 __global__ __launch_bounds__(kVecThreads) void k_dot64(const float* __restrict__ a,
                                                        const float* __restrict__ b, int64_t n,

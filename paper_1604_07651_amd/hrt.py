@@ -308,6 +308,46 @@ class Batch:
         return [packed[self.radon_off[i]:self.radon_off[i + 1]].view(d.nq, d.ntau)
                 for i, d in enumerate(self.descs)]
 
+    def _ista_args(self, f, mask, g, c2, mu, work):
+        n = len(self.descs)
+
+        def flat(x, size, name):
+            if (not isinstance(x, torch.Tensor) or x.device != self.device
+                    or x.dtype != torch.float32 or not x.is_contiguous() or x.numel() != size):
+                raise ValueError(f"{name} must be a contiguous float32 tensor of {size} "
+                                 f"elements on {self.device}")
+            return C.c_void_p(x.data_ptr())
+
+        nd, nr = self.data_off[-1], self.radon_off[-1]
+        if work is None:
+            work = (torch.empty(nd, device=self.device), torch.empty(nr, device=self.device))
+        ptrs = (flat(f, nd, "f"), flat(mask, nd, "mask") if mask is not None else None,
+                flat(g, nr, "g"), flat(work[0], nd, "work_data"), flat(work[1], nr, "work_radon"))
+        c2v = np.broadcast_to(np.asarray(c2, dtype=np.float32), (n,)).copy()
+        muv = np.broadcast_to(np.asarray(mu, dtype=np.float32), (n,)).copy()
+        as_c = lambda a: a.ctypes.data_as(C.POINTER(C.c_float))  # noqa: E731
+        return ptrs, (c2v, muv), as_c, work
+
+    def ista_iterate(self, f, g, iters: int, c2, mu, mask=None, work=None, stream=None):
+        """`iters` soft-thresholding steps for every gather at once (packed
+        arrays, in place on g); c2 and mu: one value or one per gather."""
+        ptrs, (c2v, muv), as_c, _ = self._ista_args(f, mask, g, c2, mu, work)
+        _lib.check(self._lib.hrt_batch_ista_iterate(self._h, *ptrs, int(iters), as_c(c2v),
+                                                    as_c(muv), _stream_handle(stream)),
+                   "hrt_batch_ista_iterate")
+        return g
+
+    def ista_graph(self, f, g, iters: int, c2, mu, mask=None, work=None):
+        """The same iterations captured in one HIP graph (IstaGraph)."""
+        ptrs, (c2v, muv), as_c, work = self._ista_args(f, mask, g, c2, mu, work)
+        handle = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.hrt_batch_ista_graph_create(self._h, *ptrs, int(iters),
+                                                             as_c(c2v), as_c(muv),
+                                                             C.byref(handle)),
+                       "hrt_batch_ista_graph_create")
+        return IstaGraph(self._lib, handle, (f, mask, g) + tuple(work))
+
 
 def split_edges(desc, n_t: int = 2, n_q: int = 2, first: float = 0.375):
     """Band edges for Split: time bands cut at the fractions first^(n_t-1),

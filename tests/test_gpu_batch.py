@@ -67,3 +67,77 @@ def test_batch_matches_oracle_for_one_member():
     print(f"  batch member 0 rel-L2 {r:.2e}", flush=True)
     assert r <= 1e-5
     b.close()
+
+
+def _ista_inputs(descs, seed):
+    from paper_1604_07651_amd.hrt import Batch
+    b = Batch(descs)
+    fs, masks = [], []
+    for i, d in enumerate(descs):
+        f, _ = synth.random_pair(d, seed + i, dtype=np.float32)
+        keep = synth.trace_mask(d.nx, 0.4, seed + 100 + i)
+        m = np.repeat(keep[:, None], d.nt, 1).astype(np.float32)
+        fs.append(f * m)
+        masks.append(m)
+    return b, b.pack_data(fs), b.pack_data(masks)
+
+
+def test_batch_ista_equals_per_gather_iterations():
+    """Soft-thresholding iterations for a whole batch, each gather with its
+    own step and weight, equal each gather's own iterations bit for bit."""
+    import ctypes as C
+    from paper_1604_07651_amd import _lib
+    descs = DESCS[:3] + [DESCS[4]]
+    b, F, M = _ista_inputs(descs, 70)
+    n = len(descs)
+    c2 = [0.02, 0.03, 0.015, 0.01]
+    mu = [0.5, 0.0, 1.5, 0.2]
+    G = torch.zeros(b.radon_off[-1], device="cuda")
+    print("[gpu] batch ista", flush=True)
+    b.ista_iterate(F, G, 4, c2, mu, mask=M)
+    torch.cuda.synchronize()
+    for i, d in enumerate(descs):
+        h = C.c_void_p()
+        _lib.check(b._lib.hrt_batch_plan(b._h, i, C.byref(h)), "hrt_batch_plan")
+        f = b.unpack_data(F)[i].contiguous()
+        m = b.unpack_data(M)[i].contiguous()
+        g = torch.zeros((d.nq, d.ntau), device="cuda")
+        wd = torch.empty((d.nx, d.nt), device="cuda")
+        wr = torch.empty((d.nq, d.ntau), device="cuda")
+        _lib.check(b._lib.hrt_ista_iterate(h, C.c_void_p(f.data_ptr()), C.c_void_p(m.data_ptr()),
+                                           C.c_void_p(g.data_ptr()), C.c_void_p(wd.data_ptr()),
+                                           C.c_void_p(wr.data_ptr()), 4, c2[i], mu[i], None),
+                   "hrt_ista_iterate")
+        torch.cuda.synchronize()
+        print(f"  gather {i}", flush=True)
+        assert torch.equal(b.unpack_radon(G)[i], g)
+    b.close()
+
+
+def test_batch_ista_graph_replays_match_eager():
+    """The batched iterations in one HIP graph: every replay (with eager work
+    and synchronisations between replays) equals the eager iterations."""
+    descs = [DESCS[0], DESCS[2]]
+    b, F, M = _ista_inputs(descs, 90)
+    c2, mu = [0.02, 0.025], [0.3, 0.6]
+    ref = torch.zeros(b.radon_off[-1], device="cuda")
+    print("[gpu] batch ista eager", flush=True)
+    b.ista_iterate(F, ref, 3, c2, mu, mask=M)
+    G = torch.zeros_like(ref)
+    gr = b.ista_graph(F, G, 3, c2, mu, mask=M)
+    # a later call with other parameters must not change the graph's
+    b.ista_iterate(F, torch.zeros_like(ref), 1, [0.5, 0.5], [9.0, 9.0], mask=M)
+    for rep in range(3):
+        G.zero_()
+        torch.cuda.synchronize()
+        print(f"[gpu] batch ista graph replay {rep}", flush=True)
+        gr.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(G, ref)
+        b.forward(F)  # eager work between replays
+        torch.cuda.synchronize()
+    gr.close()
+    from paper_1604_07651_amd import _lib
+    with pytest.raises(_lib.HrtError):
+        b.ista_iterate(F, G, 1, [0.02, -1.0], [0.3, 0.3], mask=M)
+    b.close()
