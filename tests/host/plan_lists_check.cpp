@@ -1,0 +1,181 @@
+// Host-side check of the plan's point lists (no GPU): for a few grids and
+// split parts, every kept data sample and every Radon sample is owned by
+// exactly one band, in index order, at a row inside that band; every
+// sample sits in the spread list of each band its 4 x 4 stencil reaches and
+// of no other; chunks tile the lists band by band within their size limits.
+// Prints "ok" and exits 0, or prints the first failure and exits 1.
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+using namespace hrt;
+
+static int fails = 0;
+#define CHECK(cond, ...)                        \
+  do {                                          \
+    if (!(cond)) {                              \
+      std::printf(__VA_ARGS__);                 \
+      std::printf("\n");                        \
+      ++fails;                                  \
+      return;                                   \
+    }                                           \
+  } while (0)
+
+// absolute lattice row of an entry of band b's list
+static double entry_row(const Geometry& g, int b, const PointEntry& e) {
+  return g.u0 + b * g.R - 2 + std::ldexp(static_cast<double>(e.yq), -kYFracBits);
+}
+
+static void check_chunks(const BandLists& L, int nb, int max_entries, const char* what) {
+  CHECK(L.off.size() == static_cast<size_t>(nb) + 1, "%s: band offsets", what);
+  CHECK(L.chunk_off.front() == 0 && L.chunk_off.back() == L.off[nb], "%s: chunk ends", what);
+  CHECK(L.band_chunk.size() == static_cast<size_t>(nb) + 1, "%s: band chunks", what);
+  for (size_t c = 0; c + 1 < L.chunk_off.size(); ++c) {
+    const int b = L.chunk_band[c];
+    CHECK(L.chunk_off[c] <= L.chunk_off[c + 1], "%s: chunk %zu order", what, c);
+    CHECK(L.chunk_off[c + 1] - L.chunk_off[c] <= max_entries, "%s: chunk %zu size", what, c);
+    CHECK(L.off[b] <= L.chunk_off[c] && L.chunk_off[c + 1] <= L.off[b + 1],
+          "%s: chunk %zu outside band %d", what, c, b);
+    CHECK(L.band_chunk[b] <= static_cast<int>(c) && static_cast<int>(c) < L.band_chunk[b + 1],
+          "%s: band_chunk of chunk %zu", what, c);
+  }
+}
+
+// `expected`: the indices the point set must hold, in increasing order
+static void check_set(const Geometry& g, const BandLists& spread, const BandLists& own,
+                      const std::vector<uint32_t>& expected, const char* what) {
+  const int nb = g.nbands;
+  check_chunks(spread, nb, kSpreadChunk, what);
+  check_chunks(own, nb, kGatherChunk, what);
+  if (fails) return;
+  // owned: each expected index once, band-major, increasing inside a band,
+  // its row floor inside the band (a row within 2^-20 of an integer may
+  // round to either side)
+  std::map<uint32_t, double> row_of;
+  for (int b = 0; b < nb; ++b) {
+    uint32_t prev = 0;
+    for (int64_t i = own.off[b]; i < own.off[b + 1]; ++i) {
+      const PointEntry& e = own.e[i];
+      CHECK(i == own.off[b] || e.idx > prev, "%s: own band %d not increasing", what, b);
+      prev = e.idx;
+      const double y = entry_row(g, b, e);
+      const int lo = g.u0 + b * g.R, hi = std::min(lo + g.R, g.u1);
+      const double fy = std::floor(y + 1e-6), fy2 = std::floor(y - 1e-6);
+      CHECK((fy >= lo && fy < hi) || (fy2 >= lo && fy2 < hi),
+            "%s: own entry %u row %.6f outside band %d [%d, %d)", what, e.idx, y, b, lo, hi);
+      CHECK(row_of.emplace(e.idx, y).second, "%s: sample %u owned twice", what, e.idx);
+      const double x = std::ldexp(static_cast<double>(e.xq), -g.x_frac_bits);
+      CHECK(x >= 1.0 - 1e-6 && x + 3.0 < g.W + 1e-6, "%s: column %.4f outside window", what, x);
+    }
+  }
+  CHECK(row_of.size() == expected.size(), "%s: %zu owned, %zu expected", what, row_of.size(),
+        expected.size());
+  for (uint32_t idx : expected) CHECK(row_of.count(idx), "%s: sample %u not owned", what, idx);
+  // spread: entry in band b iff the stencil rows floor(y)-1 .. floor(y)+2
+  // meet the band's rows; the same row as the owner's
+  std::map<uint32_t, int> seen;
+  for (int b = 0; b < nb; ++b) {
+    const int lo = g.u0 + b * g.R, hi = std::min(lo + g.R, g.u1);
+    for (int64_t i = spread.off[b]; i < spread.off[b + 1]; ++i) {
+      const PointEntry& e = spread.e[i];
+      const double y = entry_row(g, b, e);
+      CHECK(row_of.count(e.idx), "%s: spread entry %u not a sample", what, e.idx);
+      CHECK(std::fabs(y - row_of[e.idx]) < 1e-6, "%s: sample %u rows differ", what, e.idx);
+      const int iy = static_cast<int>(std::floor(y + 1e-9));
+      CHECK(iy + 2 >= lo - 1 && iy - 1 <= hi, "%s: sample %u in band %d it cannot reach", what,
+            e.idx, b);
+      ++seen[e.idx];
+    }
+  }
+  for (const auto& kv : row_of) {
+    const int iy = static_cast<int>(std::floor(kv.second));
+    int want = 0;
+    for (int b = 0; b < nb; ++b) {
+      const int lo = g.u0 + b * g.R, hi = std::min(lo + g.R, g.u1);
+      if (iy - 1 < hi && iy + 2 >= lo) ++want;
+    }
+    const int got = seen.count(kv.first) ? seen[kv.first] : 0;
+    // a row within rounding of an integer may reach one band more or less
+    CHECK(std::abs(got - want) <= 1 && got >= 1, "%s: sample %u in %d spread lists, want %d",
+          what, kv.first, got, want);
+  }
+}
+
+static void run(const char* name, const hrt_desc& d, const PartView* view) {
+  Geometry g;
+  std::string err;
+  if (build_geometry(d, 163840 - 4096, g, err, view) != HRT_OK) {
+    std::printf("%s: geometry: %s\n", name, err.c_str());
+    ++fails;
+    return;
+  }
+  PointTables t;
+  if (build_point_tables(g, t, err) != HRT_OK) {
+    std::printf("%s: tables: %s\n", name, err.c_str());
+    ++fails;
+    return;
+  }
+  const PartView& v = g.view;
+  std::vector<uint32_t> data, radon;
+  for (int k = 0; k < d.nx; ++k)
+    for (int j = std::max(g.jmin[k], v.j_lo); j < v.j_hi; ++j)
+      data.push_back(static_cast<uint32_t>(k * v.data_ld + j));
+  for (int l = 0; l < d.nq; ++l)
+    for (int i = 0; i < d.ntau; ++i)
+      radon.push_back(static_cast<uint32_t>((v.radon_row0 + l) * v.radon_ld + i));
+  if (static_cast<int64_t>(data.size()) != g.n_kept) {
+    std::printf("%s: n_kept %lld, %zu expected\n", name, static_cast<long long>(g.n_kept),
+                data.size());
+    ++fails;
+  }
+  std::string a = std::string(name) + " data", b = std::string(name) + " radon";
+  check_set(g, t.data_spread, t.data_own, data, a.c_str());
+  check_set(g, t.radon_spread, t.radon_own, radon, b.c_str());
+  if (!(t.cmax_data > 0 && t.cmax_radon > 0)) {
+    std::printf("%s: cmax\n", name);
+    ++fails;
+  }
+}
+
+int main() {
+  const double qmin = 0.25, qmax = 1.0 / 1.5;
+  hrt_desc c1{256, 128, 0.004, 0.0, 2.0 / 127, 256, 128, 0.0, 0.004, qmin,
+              (qmax - qmin) / 127, 2.0, 0};
+  hrt_desc odd{37, 23, 0.01, 0.05, 0.03, 29, 19, 0.07, 0.01, 0.3, 0.021, 2.5, 0};
+  hrt_desc ragged{301, 77, 0.004, 0.1, 0.025, 250, 61, 0.05, 0.0045, 0.22, 0.0075, 2.0, 0};
+  run("c1", c1, nullptr);
+  run("odd", odd, nullptr);
+  run("ragged", ragged, nullptr);
+  // the parts of two splits
+  const int32_t te[] = {0, 96, 256}, qe[] = {0, 64, 128};
+  const int32_t te2[] = {0, 120, 301}, qe2[] = {0, 20, 41, 61};
+  for (int p = 0; p < 4; ++p) {
+    hrt_desc sub;
+    PartView v;
+    std::string err;
+    if (split_part(c1, 2, te, 2, qe, p, sub, v, err) != HRT_OK) {
+      std::printf("c1 part %d: %s\n", p, err.c_str());
+      ++fails;
+      continue;
+    }
+    run(("c1 part " + std::to_string(p)).c_str(), sub, &v);
+  }
+  for (int p = 0; p < 6; ++p) {
+    hrt_desc sub;
+    PartView v;
+    std::string err;
+    if (split_part(ragged, 2, te2, 3, qe2, p, sub, v, err) != HRT_OK) {
+      std::printf("ragged part %d: %s\n", p, err.c_str());
+      ++fails;
+      continue;
+    }
+    run(("ragged part " + std::to_string(p)).c_str(), sub, &v);
+  }
+  if (fails) return 1;
+  std::printf("ok\n");
+  return 0;
+}
