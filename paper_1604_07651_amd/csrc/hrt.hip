@@ -857,6 +857,7 @@ struct hrt_batch_s {
   DevGeo* geos = nullptr;                    // one descriptor per gather
   int64_t* radon_off_dev = nullptr;          // radon_off on the device
   float2* ista_par = nullptr;                // (c^2, c^2 mu / 2) per gather
+  std::vector<float2> ista_par_host;         // host source of the last upload
   int2* items[kItemSets] = {};
   int nitems[kItemSets] = {};
   int spread_bytes = 0, row_bytes = 0, col_bytes = 0, gather_bytes = 0;
@@ -1097,8 +1098,10 @@ hrt_status hrt_batch_ista_iterate(hrt_batch_t b, const float* f, const float* ma
   DeviceGuard guard(b->device);
   (void)hipGetLastError();
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  HRT_HIP(hipMemcpyAsync(b->ista_par, par.data(), par.size() * sizeof(float2),
-                         hipMemcpyHostToDevice, st),
+  // the host source outlives the call, whenever the runtime performs the copy
+  b->ista_par_host = std::move(par);
+  HRT_HIP(hipMemcpyAsync(b->ista_par, b->ista_par_host.data(),
+                         b->ista_par_host.size() * sizeof(float2), hipMemcpyHostToDevice, st),
           "upload ista parameters");
   return batch_ista_enqueue(b, f, mask, g, work_data, work_radon, iters, b->ista_par, st);
 }

@@ -328,6 +328,22 @@ class Batch:
         as_c = lambda a: a.ctypes.data_as(C.POINTER(C.c_float))  # noqa: E731
         return ptrs, (c2v, muv), as_c, work
 
+    def opnorm2(self, i: int, iters: int = 30, seed: int = 0, stream=None) -> float:
+        """||R_i||^2 of gather i by float64 power iteration (for its step
+        c2_i < 1 / ||R_i||^2)."""
+        d = self.descs[i]
+        h = C.c_void_p()
+        _lib.check(self._lib.hrt_batch_plan(self._h, int(i), C.byref(h)), "hrt_batch_plan")
+        wd = torch.empty((d.nx, d.nt), device=self.device)
+        wd2 = torch.empty((d.nx, d.nt), device=self.device)
+        wr = torch.empty((d.nq, d.ntau), device=self.device)
+        out = C.c_double()
+        _lib.check(self._lib.hrt_opnorm2(h, int(iters), C.c_uint64(seed),
+                                         C.c_void_p(wd.data_ptr()), C.c_void_p(wd2.data_ptr()),
+                                         C.c_void_p(wr.data_ptr()), C.byref(out),
+                                         _stream_handle(stream)), "hrt_opnorm2")
+        return out.value
+
     def ista_iterate(self, f, g, iters: int, c2, mu, mask=None, work=None, stream=None):
         """`iters` soft-thresholding steps for every gather at once (packed
         arrays, in place on g); c2 and mu: one value or one per gather."""

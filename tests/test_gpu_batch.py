@@ -140,4 +140,8 @@ def test_batch_ista_graph_replays_match_eager():
     from paper_1604_07651_amd import _lib
     with pytest.raises(_lib.HrtError):
         b.ista_iterate(F, G, 1, [0.02, -1.0], [0.3, 0.3], mask=M)
+    # each member's operator norm, as its own plan gives it
+    from paper_1604_07651_amd.hrt import Plan
+    for i, d in enumerate(descs):
+        assert b.opnorm2(i, iters=10) == Plan(d).opnorm2(iters=10)
     b.close()
