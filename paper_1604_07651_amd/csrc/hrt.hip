@@ -129,6 +129,25 @@ std::vector<float2> twiddles(int n) {
   return t;
 }
 
+// Workgroup i of a launch runs on XCD i mod kXcds (the dispatcher deals
+// workgroups round-robin over the XCDs, each with its own L2).  A single
+// plan's row FFT and gather items are ordered so that a band's work runs on
+// one XCD: the real rows its inverse row FFT writes are read by its gather
+// chunks from the same L2.  (The spread keeps plain order: there, balance
+// over the XCDs matters more than locality.)  `per_xcd[x]` lists the items
+// of the bands given to XCD x; item i of the result comes from queue
+// i mod kXcds, and where a queue has run out the item is (0, -1), a
+// workgroup that exits at once.
+constexpr int kXcds = 8;
+std::vector<int2> xcd_order(const std::vector<std::vector<int>>& per_xcd) {
+  size_t len = 0;
+  for (const auto& q : per_xcd) len = std::max(len, q.size());
+  std::vector<int2> out(len * kXcds, make_int2(0, -1));
+  for (int x = 0; x < kXcds; ++x)
+    for (size_t k = 0; k < per_xcd[x].size(); ++k) out[k * kXcds + x] = make_int2(0, per_xcd[x][k]);
+  return out;
+}
+
 // Row-FFT items of a plan: band b's rows from s * row_rows on are item
 // (b << row_sub_shift) + s, for every s whose rows exist.
 std::vector<int> row_items(const Geometry& g) {
@@ -334,6 +353,7 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
   }
   // placed points, sorted into the band lists
   float cmax_data = 0.0f, cmax_radon = 0.0f;
+  std::vector<int32_t> chunk_band_host[4];  // band of every chunk, per list
   {
     PointTables tab;
     if ((s = build_point_tables(g, tab, err)) != HRT_OK) {
@@ -348,6 +368,7 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
                                  &tab.radon_own};
     for (int i = 0; i < 4; ++i) {
       const BandLists& L = *lists[i];
+      chunk_band_host[i] = L.chunk_band;
       p->nchunks[i] = static_cast<int>(L.chunk_band.size());
       if ((s = dev_alloc(&p->ent[i], std::max<size_t>(1, L.e.size()), total)) ||
           (s = dev_alloc(&p->chunk_off[i], L.chunk_off.size(), total)) ||
@@ -485,14 +506,39 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
     // the descriptor and the single-gather work lists on the device
     std::vector<int2> it[kItemSets];
     for (int b = 0; b < kAbsMaxBlocks; ++b) it[kItAbsmax].push_back(make_int2(0, b));
+    for (int c = 0; c < (g.K1 + g.col_batch - 1) / g.col_batch; ++c)
+      it[kItCols].push_back(make_int2(0, c));
     for (int c = 0; c < p->nchunks[kDataSpread]; ++c) it[kItSpreadData].push_back(make_int2(0, c));
     for (int c = 0; c < p->nchunks[kRadonSpread]; ++c)
       it[kItSpreadRadon].push_back(make_int2(0, c));
-    for (int r : row_items(g)) it[kItBands].push_back(make_int2(0, r));
-    for (int c = 0; c < (g.K1 + g.col_batch - 1) / g.col_batch; ++c)
-      it[kItCols].push_back(make_int2(0, c));
-    for (int c = 0; c < p->nchunks[kRadonOwn]; ++c) it[kItGatherRadon].push_back(make_int2(0, c));
-    for (int c = 0; c < p->nchunks[kDataOwn]; ++c) it[kItGatherData].push_back(make_int2(0, c));
+    // bands to XCDs: sorted by their gather chunks, dealt in snake order,
+    // so that every XCD gets as many bands (row items) as the others, and
+    // about as many gather chunks
+    std::vector<int64_t> weight(g.nbands, 0);
+    for (int32_t b : chunk_band_host[kDataOwn]) ++weight[b];
+    for (int32_t b : chunk_band_host[kRadonOwn]) ++weight[b];
+    const std::vector<int> rows = row_items(g);
+    std::vector<int> order(g.nbands), xcd(g.nbands);
+    for (int b = 0; b < g.nbands; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return weight[a] > weight[b]; });
+    for (int k = 0; k < g.nbands; ++k) {
+      const int lap = k / kXcds, pos = k % kXcds;
+      xcd[order[k]] = (lap & 1) ? kXcds - 1 - pos : pos;
+    }
+    auto by_xcd = [&](const std::vector<int32_t>& chunk_band) {
+      std::vector<std::vector<int>> q(kXcds);
+      for (size_t c = 0; c < chunk_band.size(); ++c)
+        q[xcd[chunk_band[c]]].push_back(static_cast<int>(c));
+      return xcd_order(q);
+    };
+    it[kItGatherRadon] = by_xcd(chunk_band_host[kRadonOwn]);
+    it[kItGatherData] = by_xcd(chunk_band_host[kDataOwn]);
+    {
+      std::vector<std::vector<int>> q(kXcds);
+      for (int r : rows) q[xcd[r >> g.row_sub_shift]].push_back(r);
+      it[kItBands] = xcd_order(q);
+    }
     std::vector<DevGeo> one(1, G);
     if ((s = dev_alloc(&p->geo_dev, 1, total)) || (s = upload(p->geo_dev, one))) {
       free_plan(p);
@@ -561,33 +607,34 @@ static void run_chain(hrt_plan_t p, const float* in, float* out, hipStream_t st,
   DevGeo G = p->dg;
   G.accumulate = accumulate ? 1 : 0;
   const int* ni = p->nitems;
+  int2* const* it = p->items;
   const int t0 = adjoint ? 6 : 0;  // profile slots
   if (!adjoint) {
     { StageTimer t(p, st, t0);
       k_absmax<0, false><<<ni[kItAbsmax], 256, 0, st>>>(G, nullptr, nullptr, in); }
     { StageTimer t(p, st, t0 + 1);
-      k_spread<0, false><<<ni[kItSpreadData], kNtBand, sb, st>>>(G, nullptr, nullptr, in); }
+      k_spread<0, false><<<ni[kItSpreadData], kNtBand, sb, st>>>(G, nullptr, it[kItSpreadData], in); }
     { StageTimer t(p, st, t0 + 2);
-      k_rowfft<0, false><<<ni[kItBands], kNtBand, rb, st>>>(G, nullptr, nullptr); }
+      k_rowfft<0, false><<<ni[kItBands], kNtBand, rb, st>>>(G, nullptr, it[kItBands]); }
     { StageTimer t(p, st, t0 + 3);
       k_colfft<false, false><<<ni[kItCols], kNtCol, cb, st>>>(G, nullptr, nullptr); }
     { StageTimer t(p, st, t0 + 4);
-      k_rowifft<false><<<ni[kItBands], kNtBand, rb, st>>>(G, nullptr, nullptr); }
+      k_rowifft<false><<<ni[kItBands], kNtBand, rb, st>>>(G, nullptr, it[kItBands]); }
     { StageTimer t(p, st, t0 + 5);
-      k_gather<0, false><<<ni[kItGatherRadon], kNtBand, gb, st>>>(G, nullptr, nullptr, out); }
+      k_gather<0, false><<<ni[kItGatherRadon], kNtBand, gb, st>>>(G, nullptr, it[kItGatherRadon], out); }
   } else {
     { StageTimer t(p, st, t0);
       k_absmax<1, false><<<ni[kItAbsmax], 256, 0, st>>>(G, nullptr, nullptr, in); }
     { StageTimer t(p, st, t0 + 1);
-      k_spread<1, false><<<ni[kItSpreadRadon], kNtBand, sb, st>>>(G, nullptr, nullptr, in); }
+      k_spread<1, false><<<ni[kItSpreadRadon], kNtBand, sb, st>>>(G, nullptr, it[kItSpreadRadon], in); }
     { StageTimer t(p, st, t0 + 2);
-      k_rowfft<1, false><<<ni[kItBands], kNtBand, rb, st>>>(G, nullptr, nullptr); }
+      k_rowfft<1, false><<<ni[kItBands], kNtBand, rb, st>>>(G, nullptr, it[kItBands]); }
     { StageTimer t(p, st, t0 + 3);
       k_colfft<true, false><<<ni[kItCols], kNtCol, cb, st>>>(G, nullptr, nullptr); }
     { StageTimer t(p, st, t0 + 4);
-      k_rowifft<false><<<ni[kItBands], kNtBand, rb, st>>>(G, nullptr, nullptr); }
+      k_rowifft<false><<<ni[kItBands], kNtBand, rb, st>>>(G, nullptr, it[kItBands]); }
     { StageTimer t(p, st, t0 + 5);
-      k_gather<1, false><<<ni[kItGatherData], kNtBand, gb, st>>>(G, nullptr, nullptr, out); }
+      k_gather<1, false><<<ni[kItGatherData], kNtBand, gb, st>>>(G, nullptr, it[kItGatherData], out); }
   }
 }
 

@@ -41,7 +41,9 @@ struct Work {
 template <bool BATCH>
 __device__ __forceinline__ Work work_item(const DevGeo& one, const DevGeo* __restrict__ geos,
                                           const int2* __restrict__ items) {
-  if (!BATCH) return Work{one, static_cast<int>(blockIdx.x)};
+  // a single plan's launch may come with its own order of items (negative:
+  // nothing to do); without one, item i is workgroup i
+  if (!BATCH) return Work{one, items ? items[blockIdx.x].y : static_cast<int>(blockIdx.x)};
   const int2 it = items[blockIdx.x];
   return Work{geos[it.x], it.y};
 }
@@ -129,6 +131,7 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
   extern __shared__ int lds_i[];
   __shared__ float s_wave[kNtBand / 64];
   const Work w = work_item<BATCH>(one, geos, items);
+  if (w.i < 0) return;  // a gap in the XCD-ordered items
   const DevGeo& G = w.G;
   const DevList& L = G.lists[MODE == 0 ? kDataSpread : kRadonSpread];
   const float* in = in_base + (MODE == 0 ? G.data_off : G.radon_off);
@@ -203,6 +206,7 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
   __shared__ float s_wave[kNtBand / 64];
   __shared__ float2 s_tw[kTwLds];
   const Work w = work_item<BATCH>(one, geos, items);
+  if (w.i < 0) return;  // a gap in the XCD-ordered items
   const DevGeo& G = w.G;
   const DevList& L = G.lists[MODE == 0 ? kDataSpread : kRadonSpread];
   const int band = w.i >> G.row_sub_shift;
@@ -311,6 +315,7 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo one,
   extern __shared__ float2 lds[];
   __shared__ float2 s_tw[kTwLds];
   const Work w = work_item<BATCH>(one, geos, items);
+  if (w.i < 0) return;  // a gap in the XCD-ordered items
   const DevGeo& G = w.G;
   const int band = w.i >> G.row_sub_shift;
   const int r0 = (w.i & ((1 << G.row_sub_shift) - 1)) * G.row_rows;  // first row in the band
@@ -359,6 +364,7 @@ __global__ __launch_bounds__(kNtBand) void k_gather(DevGeo one, const DevGeo* __
                                                     float* __restrict__ out_base) {
   extern __shared__ float rows[];
   const Work w = work_item<BATCH>(one, geos, items);
+  if (w.i < 0) return;  // a gap in the XCD-ordered items
   const DevGeo& G = w.G;
   const DevList& L = G.lists[MODE == 0 ? kRadonOwn : kDataOwn];
   float* out = out_base + (MODE == 0 ? G.radon_off : G.data_off);
