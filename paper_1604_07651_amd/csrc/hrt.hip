@@ -79,6 +79,10 @@ struct hrt_plan_s {
   DevGeo* geo_dev = nullptr;         // the plan's descriptor, on the device
   int2* items[kItemSets] = {};       // work items (gather 0, index)
   int nitems[kItemSets] = {};
+  // the XCD of every band (row FFT and gather items) and the band of every
+  // chunk of the two owned lists, for the XCD-aware order of batches
+  std::vector<int> band_xcd;
+  std::vector<int32_t> own_chunk_band[2];  // [0] Radon, [1] data
   // per-kernel timing (hrt_profile_begin / hrt_profile_end)
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_stage;
@@ -139,12 +143,12 @@ std::vector<float2> twiddles(int n) {
 // i mod kXcds, and where a queue has run out the item is (0, -1), a
 // workgroup that exits at once.
 constexpr int kXcds = 8;
-std::vector<int2> xcd_order(const std::vector<std::vector<int>>& per_xcd) {
+std::vector<int2> xcd_order(const std::vector<std::vector<int2>>& per_xcd) {
   size_t len = 0;
   for (const auto& q : per_xcd) len = std::max(len, q.size());
   std::vector<int2> out(len * kXcds, make_int2(0, -1));
   for (int x = 0; x < kXcds; ++x)
-    for (size_t k = 0; k < per_xcd[x].size(); ++k) out[k * kXcds + x] = make_int2(0, per_xcd[x][k]);
+    for (size_t k = 0; k < per_xcd[x].size(); ++k) out[k * kXcds + x] = per_xcd[x][k];
   return out;
 }
 
@@ -527,16 +531,19 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
       xcd[order[k]] = (lap & 1) ? kXcds - 1 - pos : pos;
     }
     auto by_xcd = [&](const std::vector<int32_t>& chunk_band) {
-      std::vector<std::vector<int>> q(kXcds);
+      std::vector<std::vector<int2>> q(kXcds);
       for (size_t c = 0; c < chunk_band.size(); ++c)
-        q[xcd[chunk_band[c]]].push_back(static_cast<int>(c));
+        q[xcd[chunk_band[c]]].push_back(make_int2(0, static_cast<int>(c)));
       return xcd_order(q);
     };
+    p->band_xcd = xcd;
+    p->own_chunk_band[0] = chunk_band_host[kRadonOwn];
+    p->own_chunk_band[1] = chunk_band_host[kDataOwn];
     it[kItGatherRadon] = by_xcd(chunk_band_host[kRadonOwn]);
     it[kItGatherData] = by_xcd(chunk_band_host[kDataOwn]);
     {
-      std::vector<std::vector<int>> q(kXcds);
-      for (int r : rows) q[xcd[r >> g.row_sub_shift]].push_back(r);
+      std::vector<std::vector<int2>> q(kXcds);
+      for (int r : rows) q[xcd[r >> g.row_sub_shift]].push_back(make_int2(0, r));
       it[kItBands] = xcd_order(q);
     }
     std::vector<DevGeo> one(1, G);
@@ -944,17 +951,28 @@ hrt_status build_batch_tables(hrt_batch_s* b, const std::vector<int>& accumulate
   }
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
   std::vector<int2> it[kItemSets];
+  // row FFT and gather items XCD-aware as for a single plan, each gather's
+  // band-to-XCD map rotated by the bands before it
+  std::vector<std::vector<int2>> qb(kXcds), qr(kXcds), qd(kXcds);
+  int rot = 0;
   for (int i : order) {
     const hrt_plan_s* pl = b->plans[i];
+    auto X = [&](int band) { return (pl->band_xcd[band] + rot) % kXcds; };
     for (int k = 0; k < kAbsMaxBlocksBatch; ++k) it[kItAbsmax].push_back(make_int2(i, k));
     for (int k = 0; k < pl->nchunks[kDataSpread]; ++k) it[kItSpreadData].push_back(make_int2(i, k));
     for (int k = 0; k < pl->nchunks[kRadonSpread]; ++k)
       it[kItSpreadRadon].push_back(make_int2(i, k));
-    for (int r : row_items(pl->g)) it[kItBands].push_back(make_int2(i, r));
+    for (int r : row_items(pl->g)) qb[X(r >> pl->g.row_sub_shift)].push_back(make_int2(i, r));
     for (int k = 0; k < pl->nitems[kItCols]; ++k) it[kItCols].push_back(make_int2(i, k));
-    for (int k = 0; k < pl->nchunks[kRadonOwn]; ++k) it[kItGatherRadon].push_back(make_int2(i, k));
-    for (int k = 0; k < pl->nchunks[kDataOwn]; ++k) it[kItGatherData].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->nchunks[kRadonOwn]; ++k)
+      qr[X(pl->own_chunk_band[0][k])].push_back(make_int2(i, k));
+    for (int k = 0; k < pl->nchunks[kDataOwn]; ++k)
+      qd[X(pl->own_chunk_band[1][k])].push_back(make_int2(i, k));
+    rot = (rot + pl->g.nbands) % kXcds;
   }
+  it[kItBands] = xcd_order(qb);
+  it[kItGatherRadon] = xcd_order(qr);
+  it[kItGatherData] = xcd_order(qd);
   for (const hrt_plan_s* pl : b->plans) {
     b->spread_bytes = std::max(b->spread_bytes, pl->g.spread_bytes);
     b->row_bytes = std::max(b->row_bytes, pl->g.row_bytes);
