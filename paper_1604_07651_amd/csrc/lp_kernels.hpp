@@ -148,9 +148,14 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
   __syncthreads();
   if (scale > 0.0f) {
     const int64_t e0 = L.chunk_off[chunk], e1 = L.chunk_off[chunk + 1];
-    // lane l of wave v takes segment (l % 8) * (kNtBand / 8) + 8 v + l / 8:
-    // the eight lane groups of a wave sit an eighth of the stage apart
-    const int seg = (threadIdx.x & 7) * (kNtBand / 8) + (threadIdx.x >> 3);
+    // data points: lane l of wave v takes segment (l % 8) * (kNtBand / 8) +
+    // 8 v + l / 8, the eight lane groups of a wave an eighth of the stage
+    // apart; Radon points (runs of one slowness share their columns):
+    // segment 101 t mod kNtBand, lanes scattered over the stage (both
+    // measured fastest for their point set)
+    const int seg = MODE == 0 ? (threadIdx.x & 7) * (kNtBand / 8) + (threadIdx.x >> 3)
+                              : (threadIdx.x * 101) & (kNtBand - 1);
+    static_assert((kNtBand & (kNtBand - 1)) == 0, "segment permutation needs a power of two");
     for (int64_t c0 = e0; c0 < e1; c0 += kSpreadStage) {
       const int n = static_cast<int>(min(static_cast<int64_t>(kSpreadStage), e1 - c0));
       for (int i = threadIdx.x; i < n; i += kNtBand) stage[i] = L.ent[c0 + i];
