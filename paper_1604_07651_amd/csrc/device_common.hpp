@@ -91,6 +91,23 @@ __device__ __forceinline__ EntryTaps decode_entry(uint32_t xq, uint32_t yq, int 
   return t;
 }
 
+// for (i = threadIdx.x; i < n; i += NT) use(i, load(i)), with the loads of
+// G consecutive iterations issued before the first of their uses: their
+// memory latencies overlap instead of adding up one iteration at a time.
+template <int NT, int G, typename Load, typename Use>
+__device__ __forceinline__ void grouped_for(int n, Load load, Use use) {
+  using T = decltype(load(0));
+  for (int i0 = static_cast<int>(threadIdx.x); i0 < n; i0 += NT * G) {
+    T v[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (i0 + g * NT < n) v[g] = load(i0 + g * NT);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (i0 + g * NT < n) use(i0 + g * NT, v[g]);
+  }
+}
+
 // LDS scratch of an FFT: null when it runs in place.
 __device__ __forceinline__ float2* fft_scratch(char* lds_base, int offset) {
   return offset < 0 ? nullptr : reinterpret_cast<float2*>(lds_base + offset);

@@ -280,32 +280,75 @@ __global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo one, const DevGeo* 
   const int nc = min(G.col_batch, G.K1 - c0);
   const int Mr = G.Mr, SP = padded_len(G.Mr);
   float2* S = G.S;
-  for (int c = 0; c < nc; ++c)
-    for (int n = threadIdx.x; n < Mr; n += kNtCol)
-      lds[c * SP + lpad(n)] = (n >= G.u0 && n < G.u1) ? S[static_cast<size_t>(c0 + c) * Mr + n]
-                                                      : make_float2(0.f, 0.f);
+  const int u0 = G.u0, U = G.u1 - G.u0, K2 = G.K2;
+  // K(k1, k2) for |k2| < K2 at position n of the column (its conjugate as
+  // the sign of k2 and the direction ask), zero outside
+  auto kval = [&](const float2* kc, int n) {
+    const int k = (n < Mr / 2) ? n : n - Mr;
+    const int ak = k < 0 ? -k : k;
+    float2 kv = make_float2(0.f, 0.f);
+    if (ak < K2) {
+      kv = kc[ak];
+      if ((k < 0) != ADJ) kv.y = -kv.y;
+    }
+    return kv;
+  };
+  auto kmul = [&](float2* lc, int n, float2 kv) {
+    const int ak = n < Mr / 2 ? n : Mr - n;
+    lc[lpad(n)] = ak < K2 ? cscale(cmul(lc[lpad(n)], kv), G.knorm) : make_float2(0.f, 0.f);
+  };
+  // One column of at most kKRegs * kNtCol points: the raw K values of its
+  // points are loaded into registers first (unconditionally, from an index
+  // clamped into the row, so that no load waits for another), and arrive
+  // while the column loads and the forward FFT run (barriers wait for LDS
+  // only); sign and range are applied at the multiply.
+  constexpr int kKRegs = 16;
+  const bool kpre = nc == 1 && Mr <= kKRegs * kNtCol;
+  float2 kr[kKRegs];
+  if (kpre) {
+    const float2* kc = G.K + static_cast<size_t>(c0) * K2;
+#pragma unroll
+    for (int g = 0; g < kKRegs; ++g) {
+      const int n = min(static_cast<int>(threadIdx.x) + g * kNtCol, Mr - 1);
+      const int ak = n < Mr / 2 ? n : Mr - n;
+      kr[g] = kc[min(ak, K2 - 1)];
+    }
+  }
+  for (int c = 0; c < nc; ++c) {
+    const float2* col = S + static_cast<size_t>(c0 + c) * Mr;
+    float2* lc = lds + c * SP;
+    grouped_for<kNtCol, 8>(
+        Mr,
+        [&](int n) { return (n >= u0 && n < u0 + U) ? col[n] : make_float2(0.f, 0.f); },
+        [&](int n, float2 v) { lc[lpad(n)] = v; });
+  }
   __syncthreads();
   float2* cscr = G.col_inplace ? nullptr : lds + SP;
   fft_rows<kNtCol, kInplaceValues, false>(lds, SP, nc, cscr, nc, G.fr, s_tw);
-  for (int c = 0; c < nc; ++c) {
-    for (int n = threadIdx.x; n < Mr; n += kNtCol) {
-      const int k = (n < Mr / 2) ? n : n - Mr;
-      const int ak = k < 0 ? -k : k;
-      float2 v = make_float2(0.f, 0.f);
-      if (ak < G.K2) {
-        float2 kv = G.K[static_cast<size_t>(c0 + c) * G.K2 + ak];
-        if ((k < 0) != ADJ) kv.y = -kv.y;
-        v = cscale(cmul(lds[c * SP + lpad(n)], kv), G.knorm);
-      }
-      lds[c * SP + lpad(n)] = v;
+  if (kpre) {
+#pragma unroll
+    for (int g = 0; g < kKRegs; ++g) {
+      const int n = static_cast<int>(threadIdx.x) + g * kNtCol;
+      float2 kv = kr[g];
+      if ((n >= Mr / 2) != ADJ) kv.y = -kv.y;  // as in kval: k2 < 0 takes conj K
+      if (n < Mr) kmul(lds, n, kv);
+    }
+  } else {
+    for (int c = 0; c < nc; ++c) {
+      const float2* kc = G.K + static_cast<size_t>(c0 + c) * K2;
+      float2* lc = lds + c * SP;
+      grouped_for<kNtCol, 8>(
+          Mr, [&](int n) { return kval(kc, n); }, [&](int n, float2 kv) { kmul(lc, n, kv); });
     }
   }
   __syncthreads();
   fft_rows<kNtCol, kInplaceValues, true>(lds, SP, nc, cscr, nc, G.fr, s_tw);
-  const int U = G.u1 - G.u0;
-  for (int c = 0; c < nc; ++c)
-    for (int n = G.u0 + threadIdx.x; n < G.u0 + U; n += kNtCol)
-      S[static_cast<size_t>(c0 + c) * Mr + n] = lds[c * SP + lpad(n)];
+  for (int c = 0; c < nc; ++c) {
+    float2* col = S + static_cast<size_t>(c0 + c) * Mr + u0;
+    const float2* lc = lds + c * SP;
+    grouped_for<kNtCol, 8>(
+        U, [&](int n) { return lc[lpad(u0 + n)]; }, [&](int n, float2 v) { col[n] = v; });
+  }
 }
 
 // Inverse row FFT of row_rows rows of a band (item i as in k_rowfft):
@@ -332,27 +375,37 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo one,
   for (int i = threadIdx.x; i < npair * SP; i += kNtBand) lds[i] = make_float2(0.f, 0.f);
   __syncthreads();
   const int psh = pair_shift(npair);
-  for (int idx = threadIdx.x; idx < (G.K1 << psh); idx += kNtBand) {
-    const int k = idx >> psh;
-    const int p = idx & ((1 << psh) - 1);
-    if (p >= npair) continue;
-    const float4 x = *reinterpret_cast<const float4*>(G.S + static_cast<size_t>(k) * G.Mr + n0 +
-                                                      2 * p);
-    // X1 = (x.x, x.y), X2 = (x.z, x.w)
-    lds[p * SP + lpad(k)] = make_float2(x.x - x.w, x.y + x.z);
-    if (k > 0) lds[p * SP + lpad(Mt - k)] = make_float2(x.x + x.w, x.z - x.y);
-  }
+  grouped_for<kNtBand, 4>(
+      G.K1 << psh,
+      [&](int idx) {
+        const int k = idx >> psh;
+        const int p = idx & ((1 << psh) - 1);
+        return p < npair ? *reinterpret_cast<const float4*>(G.S + static_cast<size_t>(k) * G.Mr +
+                                                            n0 + 2 * p)
+                         : make_float4(0.f, 0.f, 0.f, 0.f);
+      },
+      [&](int idx, float4 x) {
+        const int k = idx >> psh;
+        const int p = idx & ((1 << psh) - 1);
+        if (p >= npair) return;
+        // X1 = (x.x, x.y), X2 = (x.z, x.w)
+        lds[p * SP + lpad(k)] = make_float2(x.x - x.w, x.y + x.z);
+        if (k > 0) lds[p * SP + lpad(Mt - k)] = make_float2(x.x + x.w, x.z - x.y);
+      });
   __syncthreads();
   fft_rows<kNtBand, kInplaceValues, true>(lds, SP, npair,
                                           fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
                                           G.row_group, G.ft, s_tw);
   float* dst = G.Cr + static_cast<size_t>(n0 - G.u0) * W;
   for (int p = 0; p < npair; ++p) {
-    for (int c = threadIdx.x; c < W; c += kNtBand) {
-      const float2 z = lds[p * SP + lpad(G.xw0 + c)];
-      dst[(2 * p) * W + c] = z.x;
-      dst[(2 * p + 1) * W + c] = z.y;
-    }
+    const float2* lp = lds + p * SP;
+    float* d = dst + (2 * p) * W;
+    grouped_for<kNtBand, 4>(
+        W, [&](int c) { return lp[lpad(G.xw0 + c)]; },
+        [&](int c, float2 z) {
+          d[c] = z.x;
+          d[W + c] = z.y;
+        });
   }
 }
 
