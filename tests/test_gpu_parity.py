@@ -34,6 +34,11 @@ SMALL = {
     "wide": synth.GridDesc(nt=96, nx=1500, dt=0.004, x0=0.0, dx=4.0 / 1499, ntau=80,
                            nq=1100, tau0=0.0, dtau=0.0048, q0=0.25,
                            dq=(1 / 1.5 - 0.25) / 1099),
+    # log-radius axis of 4320 points: longer than the column kernel holds in
+    # registers (K read at the multiply) and than its in-place FFT takes
+    # (ping-pong passes)
+    "long": synth.GridDesc(nt=6000, nx=96, dt=0.0007, x0=0.0, dx=1.5 / 95, ntau=6000,
+                           nq=96, tau0=0.0, dtau=0.0007, q0=0.25, dq=(1 / 1.5 - 0.25) / 95),
 }
 
 _cache = {}
@@ -72,7 +77,8 @@ def test_kernel_multiplier_matches_oracle(name):
     assert np.abs(K - ref).max() <= 2e-7 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("name", ["c1", "odd", "tiny", "ragged", "q0zero", "wide", "c2"])
+@pytest.mark.parametrize("name", ["c1", "odd", "tiny", "ragged", "q0zero", "wide", "c2",
+                                  "long"])
 @pytest.mark.parametrize("kind", ["random", "ricker"])
 def test_forward_and_adjoint_parity(name, kind):
     desc, plan, ora = setup(name)
