@@ -226,22 +226,51 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
   const float inv = scale > 0.0f ? 1.0f / scale : 0.0f;
   const float bad = finite ? 0.0f : __int_as_float(0x7fc00000);
   const int q0 = L.band_chunk[band], q1 = L.band_chunk[band + 1];
-  for (int p = 0; p < npair; ++p) {
-    for (int m = threadIdx.x; m < Mt; m += kNtBand) {
-      const int c = m - G.xw0;
-      float lo = 0.0f, hi = 0.0f;
-      if (c >= 0 && c < W) {
-        // exact integer sums (two's complement, so order does not matter)
-        int a = 0, b = 0;
-        for (int q = q0; q < q1; ++q) {
-          const int* part = G.Hp + (static_cast<size_t>(q) * G.R + r0) * W;
-          a += part[(2 * p) * W + c];
-          b += part[(2 * p + 1) * W + c];
+  // angle columns outside the window hold no point: zero
+  for (int p = 0; p < npair; ++p)
+    for (int m = threadIdx.x; m < Mt; m += kNtBand)
+      if (m < G.xw0 || m >= G.xw0 + W) lds[p * SP + lpad(m)] = make_float2(0.0f + bad, 0.0f + bad);
+  // the window: the item's 2 npair rows are one block of 2 npair W ints in
+  // every chunk's partial (W % 4 == 0, so a 16-byte group never crosses a
+  // row); exact integer sums over the band's chunks (two's complement, so
+  // order does not matter), kGroups 16-byte groups per thread in flight
+  // together for each chunk (clamped indices: a group past the end is
+  // loaded again and not stored)
+  {
+    constexpr int kGroups = 4;
+    const int n4 = npair * W / 2;  // 16-byte groups of the block
+    float* ldsf = reinterpret_cast<float*>(lds);
+    for (int j0 = threadIdx.x; j0 < n4; j0 += kNtBand * kGroups) {
+      int4 acc[kGroups];
+#pragma unroll
+      for (int g = 0; g < kGroups; ++g) acc[g] = make_int4(0, 0, 0, 0);
+      for (int q = q0; q < q1; ++q) {
+        const int4* part =
+            reinterpret_cast<const int4*>(G.Hp + (static_cast<size_t>(q) * G.R + r0) * W);
+        int4 v[kGroups];
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g) v[g] = part[min(j0 + g * kNtBand, n4 - 1)];
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g) {
+          acc[g].x += v[g].x;
+          acc[g].y += v[g].y;
+          acc[g].z += v[g].z;
+          acc[g].w += v[g].w;
         }
-        lo = static_cast<float>(a) * inv;
-        hi = static_cast<float>(b) * inv;
       }
-      lds[p * SP + lpad(m)] = make_float2(lo + bad, hi + bad);
+#pragma unroll
+      for (int g = 0; g < kGroups; ++g) {
+        const int j = j0 + g * kNtBand;
+        if (j < n4) {
+          const int r = (4 * j) / W;       // row of the item
+          const int c = 4 * j - r * W;     // first window column of the group
+          float* dst = ldsf + 2 * ((r >> 1) * SP) + (r & 1);
+          const int a[4] = {acc[g].x, acc[g].y, acc[g].z, acc[g].w};
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            dst[2 * lpad(G.xw0 + c + t)] = static_cast<float>(a[t]) * inv + bad;
+        }
+      }
     }
   }
   __syncthreads();
