@@ -120,6 +120,20 @@ hrt_status hrt_forward(hrt_plan_t plan, const float* f, float* g,
 hrt_status hrt_adjoint(hrt_plan_t plan, const float* g, float* f,
                        void* stream);
 
+/* Normal operator: g = R_h f, then fa = R_h^T g (the forward followed by the
+ * adjoint of its output, as in the power iteration for ||R_h||^2 and in the
+ * iterative schemes of Section 3, which apply both operators in turn).
+ * f and fa are float32[nx][nt], g is
+ * float32[nq][ntau], all device pointers; both outputs are written and are
+ * bit-identical to hrt_forward(f -> g) followed by hrt_adjoint(g -> fa).
+ * One launch fewer than the two calls: the forward's last kernel also
+ * records the largest |g| that the adjoint's fixed-point scale needs.
+ * g must not overlap f or fa; fa may be f itself (f is read only before fa
+ * is written).  Same stream rules as hrt_forward; HRT_ERR_INVALID_ARG for a
+ * null or overlapping array. */
+hrt_status hrt_normal(hrt_plan_t plan, const float* f, float* g, float* fa,
+                      void* stream);
+
 /* Reference method of Section 5: direct summation over hyperbolas with
  * Keys cubic interpolation in time and the trapezoid rule in offset, in
  * float32 on the GPU (forward), and its exact transpose (adjoint).  Same

@@ -41,6 +41,7 @@ SIGNATURES = [
     ("hrt_plan_create", C.c_int, [C.POINTER(HrtDesc), C.POINTER(C.c_void_p)]),
     ("hrt_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("hrt_adjoint", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hrt_normal", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("hrt_direct_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("hrt_direct_adjoint", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("hrt_query", C.c_int, [C.c_void_p, C.POINTER(HrtInfo)]),

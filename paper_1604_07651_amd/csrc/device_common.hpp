@@ -57,6 +57,10 @@ struct DevGeo {
   int* Hp;                      // spread partial rows [chunk][R][W]
   float* Cr;                    // real rows after the inverse row FFT [u1-u0][W]
   float* absmax;                // absmax_blocks partial maxima
+  // when set, the forward gather stores the largest |output| of each of its
+  // chunks here (+inf for a non-finite output): the partial maxima of an
+  // adjoint that takes the forward's output as its input
+  float* gmax;
   const int* jmin;              // [nx_fill] first kept time sample of each trace
   DevList lists[4];
 };

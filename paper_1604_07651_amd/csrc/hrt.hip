@@ -75,6 +75,7 @@ struct hrt_plan_s {
   int* Hp = nullptr;        // partial fixed-point rows of the spread chunks
   float* Cr = nullptr;      // real lattice rows after the inverse row FFT
   float* absmax = nullptr;  // kAbsMaxBlocks partial maxima of the current input
+  float* gmax = nullptr;    // partial maxima of the forward's output, one per gather chunk
   double* dot = nullptr;    // kDotBlocks partial sums of the power iteration
   DevGeo* geo_dev = nullptr;         // the plan's descriptor, on the device
   int2* items[kItemSets] = {};       // work items (gather 0, index)
@@ -181,8 +182,8 @@ hrt_status upload(T* dst, const std::vector<T>& src) {
 }
 
 void free_plan(hrt_plan_s* p) {
-  void* ptrs[] = {p->S, p->K, p->tw_t, p->tw_r, p->jmin, p->absmax, p->Hp, p->Cr, p->dot,
-                  p->geo_dev};
+  void* ptrs[] = {p->S, p->K, p->tw_t, p->tw_r, p->jmin, p->absmax, p->gmax, p->Hp, p->Cr,
+                  p->dot, p->geo_dev};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int2* q : p->items)
@@ -399,7 +400,8 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
     const size_t parts = static_cast<size_t>(
         std::max(p->nchunks[kDataSpread], p->nchunks[kRadonSpread]));
     if ((s = dev_alloc(&p->Hp, parts * g.R * g.W, total)) ||
-        (s = dev_alloc(&p->Cr, static_cast<size_t>(g.u1 - g.u0) * g.W, total))) {
+        (s = dev_alloc(&p->Cr, static_cast<size_t>(g.u1 - g.u0) * g.W, total)) ||
+        (s = dev_alloc(&p->gmax, static_cast<size_t>(p->nchunks[kRadonOwn]), total))) {
       free_plan(p);
       delete p;
       return s;
@@ -503,6 +505,7 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
   G.ft = p->ft; G.fr = p->fr;
   G.tw_t = p->tw_t; G.tw_r = p->tw_r;
   G.K = p->K; G.S = p->S; G.Hp = p->Hp; G.Cr = p->Cr; G.absmax = p->absmax;
+  G.gmax = nullptr;
   for (int i = 0; i < 4; ++i)
     G.lists[i] = DevList{p->ent[i], p->chunk_off[i], p->chunk_band[i], p->band_chunk[i],
                          p->nchunks[i]};
@@ -606,13 +609,22 @@ struct StageTimer {
 
 // The six launches of one direction on stream `st` (arguments checked by
 // the caller; the device current).  With `accumulate` the gather adds into
-// `out` (the parts of a split after the first).
+// `out` (the parts of a split after the first).  With `chained` the two
+// directions run as R^T R: the forward's gather also stores the partial
+// maxima of its output, and the adjoint that takes that output as its
+// input uses them instead of launching its own input maximum (five
+// launches).
 static void run_chain(hrt_plan_t p, const float* in, float* out, hipStream_t st, bool adjoint,
-                      bool accumulate) {
+                      bool accumulate, bool chained = false) {
   const Geometry& g = p->g;
   const size_t sb = g.spread_bytes, rb = g.row_bytes, cb = g.col_bytes, gb = g.gather_bytes;
   DevGeo G = p->dg;
   G.accumulate = accumulate ? 1 : 0;
+  if (chained && !adjoint) G.gmax = p->gmax;
+  if (chained && adjoint) {
+    G.absmax = p->gmax;
+    G.absmax_blocks = p->nchunks[kRadonOwn];
+  }
   const int* ni = p->nitems;
   int2* const* it = p->items;
   const int t0 = adjoint ? 6 : 0;  // profile slots
@@ -630,8 +642,10 @@ static void run_chain(hrt_plan_t p, const float* in, float* out, hipStream_t st,
     { StageTimer t(p, st, t0 + 5);
       k_gather<0, false><<<ni[kItGatherRadon], kNtBand, gb, st>>>(G, nullptr, it[kItGatherRadon], out); }
   } else {
-    { StageTimer t(p, st, t0);
-      k_absmax<1, false><<<ni[kItAbsmax], 256, 0, st>>>(G, nullptr, nullptr, in); }
+    if (!chained) {
+      StageTimer t(p, st, t0);
+      k_absmax<1, false><<<ni[kItAbsmax], 256, 0, st>>>(G, nullptr, nullptr, in);
+    }
     { StageTimer t(p, st, t0 + 1);
       k_spread<1, false><<<ni[kItSpreadRadon], kNtBand, sb, st>>>(G, nullptr, it[kItSpreadRadon], in); }
     { StageTimer t(p, st, t0 + 2);
@@ -792,6 +806,24 @@ void hrt_graph_destroy(hrt_graph_t gr) {
   delete gr;
 }
 
+hrt_status hrt_normal(hrt_plan_t p, const float* f, float* g, float* fa, void* stream) {
+  hrt_status s = check_plan(p);
+  if (s != HRT_OK) return s;
+  if (!f || !g || !fa) return set_err(HRT_ERR_INVALID_ARG, "null array");
+  const size_t nd = static_cast<size_t>(p->g.d.nx) * p->g.d.nt * sizeof(float);
+  const size_t nr = static_cast<size_t>(p->g.d.nq) * p->g.d.ntau * sizeof(float);
+  if (overlaps(f, nd, g, nr) || overlaps(g, nr, fa, nd))
+    return set_err(HRT_ERR_INVALID_ARG, "input and output overlap");
+  DeviceGuard guard(p->device);
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  run_chain(p, f, g, st, false, false, true);
+  run_chain(p, g, fa, st, true, false, true);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(e, "normal launch");
+  return HRT_OK;
+}
+
 hrt_status hrt_opnorm2(hrt_plan_t p, int32_t iters, uint64_t seed, float* work_data,
                        float* work_data2, float* work_radon, double* out, void* stream) {
   hrt_status s = check_plan(p);
@@ -835,8 +867,7 @@ hrt_status hrt_opnorm2(hrt_plan_t p, int32_t iters, uint64_t seed, float* work_d
                                                        n_data);
   for (int it = 0; it < iters; ++it) {
     // w = R* R v, lambda = <v, w> for |v| = 1, then v = w / |w|
-    if ((s = launch_chain(p, work_data, work_radon, stream, false)) != HRT_OK) return s;
-    if ((s = launch_chain(p, work_radon, work_data2, stream, true)) != HRT_OK) return s;
+    if ((s = hrt_normal(p, work_data, work_radon, work_data2, stream)) != HRT_OK) return s;
     double vw = 0.0, ww = 0.0;
     if ((s = dot(work_data, work_data2, vw)) != HRT_OK) return s;
     if ((s = dot(work_data2, work_data2, ww)) != HRT_OK) return s;

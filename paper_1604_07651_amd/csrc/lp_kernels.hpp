@@ -450,6 +450,7 @@ __global__ __launch_bounds__(kNtBand) void k_gather(DevGeo one, const DevGeo* __
                                                     const int2* __restrict__ items,
                                                     float* __restrict__ out_base) {
   extern __shared__ float rows[];
+  __shared__ float s_wave[kNtBand / 64];
   const Work w = work_item<BATCH>(one, geos, items);
   if (w.i < 0) return;  // a gap in the XCD-ordered items
   const DevGeo& G = w.G;
@@ -469,6 +470,7 @@ __global__ __launch_bounds__(kNtBand) void k_gather(DevGeo one, const DevGeo* __
   const int64_t e0 = L.chunk_off[chunk], e1 = L.chunk_off[chunk + 1];
   const int shift = n0 - L0;  // held row of lattice row n0
   const int nheld = L1 - L0;
+  float vmax = 0.0f;  // largest |output| of this thread (forward)
   for (int64_t e = e0 + threadIdx.x; e < e1; e += kNtBand) {
     const uint4 E = L.ent[e];
     const EntryTaps tp = decode_entry(E.y, E.z, G.x_frac_bits);
@@ -482,6 +484,11 @@ __global__ __launch_bounds__(kNtBand) void k_gather(DevGeo one, const DevGeo* __
     }
     const float v = __uint_as_float(E.w) * acc;
     out[E.x] = G.accumulate ? out[E.x] + v : v;
+    if (MODE == 0) vmax = fmaxf(vmax, fabsf(v) <= 3.0e38f ? fabsf(v) : INFINITY);
+  }
+  if (MODE == 0 && G.gmax) {
+    vmax = block_max(vmax, s_wave);
+    if (threadIdx.x == 0) G.gmax[chunk] = vmax;
   }
   if (MODE == 1 && !G.accumulate) {
     for (int k = chunk; k < G.nx_fill; k += L.nchunks) {

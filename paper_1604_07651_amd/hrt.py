@@ -90,6 +90,23 @@ class Plan:
         return self._call(self._lib.hrt_adjoint, g, out, self.radon_shape,
                           self.data_shape, stream, "hrt_adjoint")
 
+    def normal(self, f: torch.Tensor, g=None, out=None, stream=None):
+        """g = R_h f and R_h^T g in one call (hrt_normal): f (nx, nt) -> (g (nq, ntau),
+        R_h^T g (nx, nt)); out may be f itself."""
+        self._check_in(f, self.data_shape, "input")
+        if g is None:
+            g = torch.empty(self.radon_shape, dtype=torch.float32, device=self.device)
+        else:
+            self._check_in(g, self.radon_shape, "g")
+        if out is None:
+            out = torch.empty(self.data_shape, dtype=torch.float32, device=self.device)
+        else:
+            self._check_in(out, self.data_shape, "out")
+        _lib.check(self._lib.hrt_normal(self._h, C.c_void_p(f.data_ptr()),
+                                        C.c_void_p(g.data_ptr()), C.c_void_p(out.data_ptr()),
+                                        _stream_handle(stream)), "hrt_normal")
+        return g, out
+
     def direct_forward(self, f: torch.Tensor, out=None, stream=None) -> torch.Tensor:
         """Direct summation over hyperbolas (float32 GPU reference method)."""
         return self._call(self._lib.hrt_direct_forward, f, out, self.data_shape,

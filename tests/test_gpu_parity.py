@@ -136,6 +136,45 @@ def test_full_size_parity(name):
     compare(fa.cpu().numpy(), ora.adjoint(g_np), f"adjoint {name}")
 
 
+@pytest.mark.parametrize("name", ["c1", "ragged", "q0zero", "c2", "long", "c3"])
+def test_normal_equals_forward_then_adjoint(name):
+    """hrt_normal (the adjoint's input maximum taken from the forward's
+    gather) gives exactly the two separate calls, also with fa over f."""
+    desc, plan, ora = setup(name)
+    f = to_gpu(synth.random_pair(desc, 31)[0])
+    print(f"[gpu] normal {name}", flush=True)
+    g1 = plan.forward(f)
+    fa1 = plan.adjoint(g1)
+    g2, fa2 = plan.normal(f)
+    f3 = f.clone()
+    g3, fa3 = plan.normal(f3, out=f3)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2) and torch.equal(fa1, fa2)
+    assert torch.equal(g1, g3) and torch.equal(fa1, fa3)
+
+
+def test_normal_non_finite_zero_and_overlap():
+    from paper_1604_07651_amd import _lib
+    desc, plan, ora = setup("c1")
+    print("[gpu] normal: zero, non-finite, overlap", flush=True)
+    f = np.zeros((desc.nx, desc.nt), dtype=np.float32)
+    g, fa = plan.normal(to_gpu(f))
+    torch.cuda.synchronize()
+    assert not g.any() and not fa.any()
+    f[3, 100] = np.inf
+    g, fa = plan.normal(to_gpu(f))
+    torch.cuda.synchronize()
+    assert torch.isnan(g).all()
+    assert torch.isnan(fa[torch.from_numpy(ora.geo.keep).cuda()]).all()
+    # g overlapping f is refused before anything is launched
+    nd, nr = desc.nx * desc.nt, desc.nq * desc.ntau
+    buf = torch.zeros(nd + nr, device="cuda")
+    fv = buf[:nd].view(desc.nx, desc.nt)
+    gv = buf[nd - 8:nd - 8 + nr].view(desc.nq, desc.ntau)
+    with pytest.raises(_lib.HrtError):
+        plan.normal(fv, g=gv)
+
+
 def test_non_finite_input_gives_nan_everywhere():
     """One NaN or inf in the input makes the whole output NaN (the spread's
     fixed-point scale cannot be formed), in both directions."""

@@ -83,6 +83,7 @@ def test_status_strings_and_bad_handles():
     # a pointer that is no live plan is refused without being dereferenced
     bogus = C.c_void_p(0x1234)
     assert lib.hrt_forward(bogus, None, None, None) == 5
+    assert lib.hrt_normal(bogus, None, None, None, None) == 5
     assert lib.hrt_query(None, None) == 1
     lib.hrt_plan_destroy(bogus)   # ignored
 
