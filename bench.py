@@ -1,10 +1,13 @@
 #!/usr/bin/env python3
 """Throughput of the log-polar hyperbolic Radon transform on one MI355X.
 
-A step is one forward plus one adjoint transform of a device-resident CMP
-gather: 2048 time samples (dt = 2 ms) x 1024 offsets (0..4 km) -> Radon panel
-2048 taus x 1024 slownesses (v in [1.5, 4] km/s), 100 Ricker events at 30 Hz,
-log-polar lattice 2160 x 3072 (oversampling 2).  Prints one JSON line.
+A step is one forward transform of a device-resident CMP gather and the
+adjoint transform of its output (g = R f, then R^T g, through hrt_normal;
+the same two results as hrt_forward followed by hrt_adjoint, bit for bit,
+whose time is reported beside it): 2048 time samples (dt = 2 ms) x 1024
+offsets (0..4 km) -> Radon panel 2048 taus x 1024 slownesses (v in
+[1.5, 4] km/s), 100 Ricker events at 30 Hz, log-polar lattice 2160 x 3072
+(oversampling 2).  Prints one JSON line.
 
 Beside the throughput it reports: per-kernel HIP-event timings and the HBM
 roofline of the dominant kernel, the float32 GPU direct summation over
@@ -432,6 +435,9 @@ def main():
     fa = torch.empty(plan.data_shape, device="cuda")
 
     def step():
+        plan.normal(f, g=g, out=fa)
+
+    def step_two_calls():
         plan.forward(f, out=g)
         plan.adjoint(g, out=fa)
 
@@ -447,6 +453,15 @@ def main():
     t1 = time.perf_counter()
     sec_per_step = (t1 - t0) / args.steps
     value = 1.0 / sec_per_step
+    # the same step as two calls (the adjoint with its own input maximum)
+    for _ in range(args.warmup):
+        step_two_calls()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_two_calls()
+    torch.cuda.synchronize()
+    sec_two_calls = (time.perf_counter() - t0) / args.steps
 
     # per-kernel HIP events on the launch stream, over the same number of steps
     log("per-kernel event timing")
@@ -488,6 +503,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(sec_per_step * 1e3, 5),
+        "ms_per_step_two_calls": round(sec_two_calls * 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
