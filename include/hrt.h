@@ -285,14 +285,15 @@ hrt_status hrt_plan_kernel(hrt_plan_t plan, float* host_out);
 
 /* Per-kernel timing for measurement tools.  hrt_profile_begin creates
  * 2*max_records HIP events (the only allocation; none happens later) and
- * from then on hrt_forward / hrt_adjoint record an event on the launch
- * stream before and after each of their kernels, until max_records kernels
- * have been recorded.  hrt_profile_end synchronizes on the recorded events,
- * writes the summed milliseconds and the launch count per kernel into
- * ms_sum[HRT_PROFILE_SLOTS] and count[HRT_PROFILE_SLOTS] (order: forward
- * input maximum, spread, row FFT, column pass, row inverse FFT, gather, then
- * the same six of the adjoint) and releases the events.  Either output may
- * be NULL. */
+ * from then on hrt_forward / hrt_adjoint / hrt_normal record an event on
+ * the launch stream before and after each of their kernels, until
+ * max_records kernels have been recorded.  hrt_profile_end synchronizes on
+ * the recorded events, writes the summed milliseconds and the launch count
+ * per kernel into ms_sum[HRT_PROFILE_SLOTS] and count[HRT_PROFILE_SLOTS]
+ * (order: forward input maximum, spread, row FFT, column pass, row inverse
+ * FFT, gather, then the same six of the adjoint; hrt_normal launches no
+ * adjoint input maximum) and releases the events.  Either output may be
+ * NULL. */
 #define HRT_PROFILE_SLOTS 12
 hrt_status hrt_profile_begin(hrt_plan_t plan, int32_t max_records);
 hrt_status hrt_profile_end(hrt_plan_t plan, double* ms_sum, int64_t* count);
