@@ -254,6 +254,37 @@ def ista_c5(torch, np, iters=100, mu_rel=0.01):
             "snr_all_db": round(float(np.mean(snr_a)), 2), "hip_graph": True}
 
 
+def batch_c3(torch, np, n=8, reps=20):
+    """n gathers of the C3 shape (drawn like C3, seeds 3 .. 3 + n - 1) in one
+    batch: forward+adjoint of all of them with one launch per kernel, the
+    throughput of a survey's gathers taken n at a time (the headline value is
+    one gather per call)."""
+    import synth
+    from paper_1604_07651_amd.hrt import Batch
+    desc = synth.config_desc("c3")
+    b = Batch([desc] * n)
+    from synth.gathers import CONFIGS
+    c = CONFIGS["c3"]
+    F = b.pack_data([synth.ricker_gather(desc, c["events"], c["freq"], c["seed"] + i, c["tau"],
+                                         noise=c["noise"], dtype=np.float32)
+                     for i in range(n)])
+    g = b.forward(F)
+    fa = b.adjoint(g)
+    for _ in range(2):
+        b.forward(F, out=g)
+        b.adjoint(g, out=fa)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.forward(F, out=g)
+        b.adjoint(g, out=fa)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    b.close()
+    return {"gathers": n, "ms_per_batch": round(sec * 1e3, 3),
+            "gathers_per_s": round(n / sec, 1)}
+
+
 def batch_c4(torch, np, n=64, reps=10):
     """Uneven batch: n gathers (nt in {512, 1024, 2048}, nx in 128..1024),
     forward+adjoint of the whole batch with one launch per kernel, against
@@ -540,6 +571,8 @@ def main():
     if not args.no_batch:
         log("uneven batch: 64 gathers, one launch per kernel vs one call per gather")
         out["batch_c4"] = batch_c4(torch, np)
+        log("batch of C3 gathers")
+        out["batch_c3"] = batch_c3(torch, np)
 
     if not args.no_ista:
         log("trace interpolation: 16 gathers x 100 iterations in HIP graphs")
