@@ -20,6 +20,10 @@ DESCS = [
     synth.GridDesc(nt=16, nx=16, dt=0.01, x0=0.0, dx=0.02, ntau=16, nq=16,
                    tau0=0.0, dtau=0.01, q0=0.25, dq=(1 / 1.5 - 0.25) / 15),
     synth.config_desc("c2"),
+    # a 4320-point log-radius axis: the column kernel's paths for columns it
+    # cannot hold in registers or transform in place, in the batched launch
+    synth.GridDesc(nt=6000, nx=96, dt=0.0007, x0=0.0, dx=1.5 / 95, ntau=6000, nq=96,
+                   tau0=0.0, dtau=0.0007, q0=0.25, dq=(1 / 1.5 - 0.25) / 95),
 ]
 
 
