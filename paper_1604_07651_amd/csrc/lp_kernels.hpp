@@ -471,16 +471,26 @@ __global__ __launch_bounds__(kNtBand) void k_gather(DevGeo one, const DevGeo* __
   const int shift = n0 - L0;  // held row of lattice row n0
   const int nheld = L1 - L0;
   float vmax = 0.0f;  // largest |output| of this thread (forward)
+  // each thread's next entry is in flight while it interpolates the current
+  // one (indices clamped into the chunk, into entry 0 for an empty chunk:
+  // every device list holds at least one entry; a load past the end is
+  // never used)
+  const int64_t last = e1 > 0 ? e1 - 1 : 0;
+  uint4 En = L.ent[min(e0 + static_cast<int64_t>(threadIdx.x), last)];
   for (int64_t e = e0 + threadIdx.x; e < e1; e += kNtBand) {
-    const uint4 E = L.ent[e];
+    const uint4 E = En;
+    En = L.ent[min(e + kNtBand, last)];
     const EntryTaps tp = decode_entry(E.y, E.z, G.x_frac_bits);
     float acc = 0.0f;
+    // the four tap rows without branches: a row outside the held ones
+    // (beyond the used lattice rows) reads held row 0 with weight 0
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
       const int rl = tp.cy + shift + bb;
-      if (rl < 0 || rl >= nheld) continue;
-      const float* r = rows + rl * W + tp.cx;
-      acc += tp.wy[bb] * (r[0] * tp.wx[0] + r[1] * tp.wx[1] + r[2] * tp.wx[2] + r[3] * tp.wx[3]);
+      const bool held = rl >= 0 && rl < nheld;
+      const float* r = rows + (held ? rl : 0) * W + tp.cx;
+      const float wy = held ? tp.wy[bb] : 0.0f;
+      acc += wy * (r[0] * tp.wx[0] + r[1] * tp.wx[1] + r[2] * tp.wx[2] + r[3] * tp.wx[3]);
     }
     const float v = __uint_as_float(E.w) * acc;
     out[E.x] = G.accumulate ? out[E.x] + v : v;
