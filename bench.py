@@ -522,9 +522,21 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.direct_steps):
         plan.direct_forward(f, out=gd)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.direct_steps):
         plan.direct_adjoint(g, out=fd)
     torch.cuda.synchronize()
-    direct_sec = (time.perf_counter() - t0) / args.direct_steps
+    direct_fwd_sec = (t1 - t0) / args.direct_steps
+    direct_sec = direct_fwd_sec + (time.perf_counter() - t1) / args.direct_steps
+    # the log-polar forward alone, for the forward-only ratio (the direct
+    # adjoint, a gather over all slownesses with a tau-range search per
+    # sample, costs several times the direct forward)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.forward(f, out=g)
+    torch.cuda.synchronize()
+    lp_fwd_sec = (time.perf_counter() - t0) / args.steps
 
     out = {
         "metric": METRIC,
@@ -555,7 +567,10 @@ def main():
         "kernel_source_hash": kernel_source_hash(),
         "direct_sum": {"gathers_per_s": round(1.0 / direct_sec, 3),
                        "ms_fwd_adj": round(direct_sec * 1e3, 3),
-                       "speedup_log_polar": round(direct_sec / sec_per_step, 1)},
+                       "ms_fwd": round(direct_fwd_sec * 1e3, 3),
+                       "ms_adj": round((direct_sec - direct_fwd_sec) * 1e3, 3),
+                       "speedup_log_polar": round(direct_sec / sec_per_step, 1),
+                       "speedup_log_polar_fwd": round(direct_fwd_sec / lp_fwd_sec, 1)},
     }
 
     if not args.no_split:
