@@ -19,7 +19,9 @@ constexpr int kAbsMaxBlocksBatch = 64; // ... per gather of a batch
 // The four point lists of a plan, cut into chunks (see BandLists).
 enum { kDataSpread = 0, kDataOwn = 1, kRadonSpread = 2, kRadonOwn = 3 };
 struct DevList {
-  const uint4* ent;
+  const uint4* ent;   // 16-byte entries (data lists)
+  const uint2* ent2;  // Radon lists: {sample index, log-radius coordinate}; the
+                      // angle coordinate and weight are the slowness's (q_tab)
   const int64_t* chunk_off;
   const int* chunk_band;
   const int* band_chunk;
@@ -61,6 +63,12 @@ struct DevGeo {
   // chunks here (+inf for a non-finite output): the partial maxima of an
   // adjoint that takes the forward's output as its input
   float* gmax;
+  // per slowness of the plan: {angle coordinate, weight bits} of its Radon
+  // points; a Radon sample index idx lies in array row
+  // (idx * rdiv_m) >> rdiv_s = idx / radon_ld (exact for idx < 2^32)
+  const uint2* q_tab;
+  uint64_t rdiv_m;
+  int rdiv_s;
   const int* jmin;              // [nx_fill] first kept time sample of each trace
   DevList lists[4];
 };
@@ -110,6 +118,16 @@ __device__ __forceinline__ void grouped_for(int n, Load load, Use use) {
     for (int g = 0; g < G; ++g)
       if (i0 + g * NT < n) use(i0 + g * NT, v[g]);
   }
+}
+
+// The full entry {idx, angle, log radius, weight} of a compact Radon entry
+// {idx, log radius}: the slowness row from the index, its angle coordinate
+// and weight from the plan's table (the row clamped into the table).
+__device__ __forceinline__ uint4 radon_entry(const DevGeo& G, uint2 e) {
+  const uint64_t row = (static_cast<uint64_t>(e.x) * G.rdiv_m) >> G.rdiv_s;
+  const int l = min(max(static_cast<int>(row) - G.radon_row0, 0), G.nq - 1);
+  const uint2 t = G.q_tab[l];
+  return make_uint4(e.x, t.x, e.y, t.y);
 }
 
 // LDS scratch of an FFT: null when it runs in place.

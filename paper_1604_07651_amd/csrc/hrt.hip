@@ -67,7 +67,11 @@ struct hrt_plan_s {
   float2* tw_r = nullptr;
   int* jmin = nullptr;
   // point lists (kDataSpread ... kRadonOwn), cut into chunks
-  uint4* ent[4] = {};
+  uint4* ent[4] = {};       // data lists: 16-byte entries
+  uint2* ent2[4] = {};      // Radon lists: {sample index, log-radius coordinate}
+  uint2* q_tab = nullptr;   // per slowness: {angle coordinate, weight bits}
+  uint64_t rdiv_m = 0;      // idx / radon_ld = (idx * rdiv_m) >> rdiv_s
+  int rdiv_s = 0;
   int64_t* chunk_off[4] = {};
   int* chunk_band[4] = {};
   int* band_chunk[4] = {};
@@ -183,13 +187,14 @@ hrt_status upload(T* dst, const std::vector<T>& src) {
 
 void free_plan(hrt_plan_s* p) {
   void* ptrs[] = {p->S, p->K, p->tw_t, p->tw_r, p->jmin, p->absmax, p->gmax, p->Hp, p->Cr,
-                  p->dot, p->geo_dev};
+                  p->dot, p->geo_dev, p->q_tab};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int2* q : p->items)
     if (q) (void)hipFree(q);
   for (int i = 0; i < 4; ++i) {
-    void* lists[] = {p->ent[i], p->chunk_off[i], p->chunk_band[i], p->band_chunk[i]};
+    void* lists[] = {p->ent[i], p->ent2[i], p->chunk_off[i], p->chunk_band[i],
+                     p->band_chunk[i]};
     for (void* q : lists)
       if (q) (void)hipFree(q);
   }
@@ -371,22 +376,57 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
     cmax_radon = static_cast<float>(tab.cmax_radon * (1.0 + 1e-5));
     const BandLists* lists[4] = {&tab.data_spread, &tab.data_own, &tab.radon_spread,
                                  &tab.radon_own};
+    // Radon lists travel as {sample index, log-radius coordinate}: a Radon
+    // point's angle coordinate and weight are its slowness's, so they sit
+    // once per slowness in q_tab.  The row of an index comes from a
+    // multiply-shift division, checked here against the exact one for
+    // every entry.
+    const uint64_t ld = static_cast<uint64_t>(g.view.radon_ld);
+    int lg = 0;
+    while ((uint64_t{1} << lg) < ld) ++lg;
+    p->rdiv_s = 32 + lg;
+    p->rdiv_m = ((uint64_t{1} << p->rdiv_s) + ld - 1) / ld;
+    std::vector<uint2> qtab(static_cast<size_t>(std::max(g.d.nq, 1)), make_uint2(0u, 0u));
+    std::vector<char> qseen(qtab.size(), 0);
     for (int i = 0; i < 4; ++i) {
       const BandLists& L = *lists[i];
+      const bool radon = i == kRadonSpread || i == kRadonOwn;
       chunk_band_host[i] = L.chunk_band;
       p->nchunks[i] = static_cast<int>(L.chunk_band.size());
-      if ((s = dev_alloc(&p->ent[i], std::max<size_t>(1, L.e.size()), total)) ||
+      std::vector<uint2> compact;
+      if (radon) {
+        compact.resize(L.e.size());
+        for (size_t k = 0; k < L.e.size(); ++k) {
+          const PointEntry& E = L.e[k];
+          const uint64_t row = E.idx / ld;
+          const int l = static_cast<int>(row) - g.view.radon_row0;
+          uint32_t wbits;
+          std::memcpy(&wbits, &E.w, sizeof wbits);
+          if (((static_cast<uint64_t>(E.idx) * p->rdiv_m) >> p->rdiv_s) != row || l < 0 ||
+              l >= g.d.nq || (qseen[l] && (qtab[l].x != E.xq || qtab[l].y != wbits))) {
+            free_plan(p);
+            delete p;
+            return set_err(HRT_ERR_GEOMETRY, "Radon point entries disagree with their slowness");
+          }
+          qtab[l] = make_uint2(E.xq, wbits);
+          qseen[l] = 1;
+          compact[k] = make_uint2(E.idx, E.yq);
+        }
+      }
+      if ((!radon && (s = dev_alloc(&p->ent[i], std::max<size_t>(1, L.e.size()), total))) ||
+          (radon && (s = dev_alloc(&p->ent2[i], std::max<size_t>(1, compact.size()), total))) ||
           (s = dev_alloc(&p->chunk_off[i], L.chunk_off.size(), total)) ||
           (s = dev_alloc(&p->chunk_band[i], L.chunk_band.size(), total)) ||
           (s = dev_alloc(&p->band_chunk[i], L.band_chunk.size(), total)) ||
           (s = upload(p->chunk_off[i], L.chunk_off)) ||
           (s = upload(p->chunk_band[i], L.chunk_band)) ||
-          (s = upload(p->band_chunk[i], L.band_chunk))) {
+          (s = upload(p->band_chunk[i], L.band_chunk)) ||
+          (radon && (s = upload(p->ent2[i], compact)))) {
         free_plan(p);
         delete p;
         return s;
       }
-      if (!L.e.empty()) {
+      if (!radon && !L.e.empty()) {
         hipError_t e = hipMemcpy(p->ent[i], L.e.data(), L.e.size() * sizeof(PointEntry),
                                  hipMemcpyHostToDevice);
         if (e != hipSuccess) {
@@ -395,6 +435,11 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
           return hip_err(e, "upload point lists");
         }
       }
+    }
+    if ((s = dev_alloc(&p->q_tab, qtab.size(), total)) || (s = upload(p->q_tab, qtab))) {
+      free_plan(p);
+      delete p;
+      return s;
     }
     // one partial per spread chunk, and the real rows after the inverse FFT
     const size_t parts = static_cast<size_t>(
@@ -506,9 +551,12 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
   G.tw_t = p->tw_t; G.tw_r = p->tw_r;
   G.K = p->K; G.S = p->S; G.Hp = p->Hp; G.Cr = p->Cr; G.absmax = p->absmax;
   G.gmax = nullptr;
+  G.q_tab = p->q_tab;
+  G.rdiv_m = p->rdiv_m;
+  G.rdiv_s = p->rdiv_s;
   for (int i = 0; i < 4; ++i)
-    G.lists[i] = DevList{p->ent[i], p->chunk_off[i], p->chunk_band[i], p->band_chunk[i],
-                         p->nchunks[i]};
+    G.lists[i] = DevList{p->ent[i], p->ent2[i], p->chunk_off[i], p->chunk_band[i],
+                         p->band_chunk[i], p->nchunks[i]};
   {
     // the descriptor and the single-gather work lists on the device
     std::vector<int2> it[kItemSets];

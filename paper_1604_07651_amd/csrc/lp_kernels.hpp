@@ -158,7 +158,12 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
     static_assert((kNtBand & (kNtBand - 1)) == 0, "segment permutation needs a power of two");
     for (int64_t c0 = e0; c0 < e1; c0 += kSpreadStage) {
       const int n = static_cast<int>(min(static_cast<int64_t>(kSpreadStage), e1 - c0));
-      for (int i = threadIdx.x; i < n; i += kNtBand) stage[i] = L.ent[c0 + i];
+      if (MODE == 1) {  // compact Radon entries
+        uint2* stage2 = reinterpret_cast<uint2*>(stage);
+        for (int i = threadIdx.x; i < n; i += kNtBand) stage2[i] = L.ent2[c0 + i];
+      } else {
+        for (int i = threadIdx.x; i < n; i += kNtBand) stage[i] = L.ent[c0 + i];
+      }
       __syncthreads();
       const int per = (n + kNtBand - 1) / kNtBand;
       int p = seg * per;
@@ -167,7 +172,10 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
         uint4 E[4];
         float v[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) E[t] = (p + t < pend) ? stage[p + t] : make_uint4(0, 0, 0, 0);
+        for (int t = 0; t < 4; ++t)
+          E[t] = (p + t >= pend) ? make_uint4(0, 0, 0, 0)
+                 : MODE == 1     ? radon_entry(G, reinterpret_cast<const uint2*>(stage)[p + t])
+                                 : stage[p + t];
 #pragma unroll
         for (int t = 0; t < 4; ++t) v[t] = (p + t < pend) ? in[E[t].x] : 0.0f;
 #pragma unroll
@@ -476,10 +484,19 @@ __global__ __launch_bounds__(kNtBand) void k_gather(DevGeo one, const DevGeo* __
   // every device list holds at least one entry; a load past the end is
   // never used)
   const int64_t last = e1 > 0 ? e1 - 1 : 0;
-  uint4 En = L.ent[min(e0 + static_cast<int64_t>(threadIdx.x), last)];
+  // (the forward's Radon points come as compact entries, expanded once
+  // they have arrived)
+  auto raw = [&](int64_t k) {
+    if (MODE == 0) {
+      const uint2 c = L.ent2[k];
+      return make_uint4(c.x, c.y, 0u, 0u);
+    }
+    return L.ent[k];
+  };
+  uint4 En = raw(min(e0 + static_cast<int64_t>(threadIdx.x), last));
   for (int64_t e = e0 + threadIdx.x; e < e1; e += kNtBand) {
-    const uint4 E = En;
-    En = L.ent[min(e + kNtBand, last)];
+    const uint4 E = MODE == 0 ? radon_entry(G, make_uint2(En.x, En.y)) : En;
+    En = raw(min(e + kNtBand, last));
     const EntryTaps tp = decode_entry(E.y, E.z, G.x_frac_bits);
     float acc = 0.0f;
     // the four tap rows without branches: a row outside the held ones
