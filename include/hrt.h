@@ -92,7 +92,8 @@ typedef struct {
   int32_t row_lo, row_hi;         /* lattice rows the data and outputs use  */
   int32_t band_rows, n_bands;     /* row bands of the spread/gather kernels */
   int64_t n_kept;                 /* data samples inside the trapezoid      */
-  int64_t workspace_bytes;        /* device memory owned by the plan        */
+  int64_t workspace_bytes;        /* device memory owned by the plan (0 from
+                                     hrt_plan_describe: nothing allocated)  */
   double alg_bytes_fwd;           /* algorithmic HBM bytes of one forward   */
   double alg_bytes_adj;           /* ... and of one adjoint                 */
 } hrt_info;
