@@ -2,7 +2,8 @@
 // split parts, every kept data sample and every Radon sample is owned by
 // exactly one band, in index order, at a row inside that band; every
 // sample sits in the spread list of each band its 4 x 4 stencil reaches and
-// of no other; chunks tile the lists band by band within their size limits.
+// of no other; chunks tile the lists band by band within their size limits;
+// the Radon entries of one slowness share their angle coordinate and weight.
 // Prints "ok" and exits 0, or prints the first failure and exits 1.
 #include <cmath>
 #include <cstdio>
@@ -105,6 +106,37 @@ static void check_set(const Geometry& g, const BandLists& spread, const BandList
   }
 }
 
+// Radon entries travel to the device without their angle coordinate and
+// weight, which are taken from a per-slowness table: every Radon entry of
+// one slowness (in both lists) must carry the same pair, and the slowness
+// row of an index, (idx * m) >> s with s = 32 + ceil(log2 ld) and
+// m = ceil(2^s / ld), must be idx / ld exactly.
+static void check_radon_slowness(const Geometry& g, const BandLists& spread,
+                                 const BandLists& own, const char* what) {
+  const PartView& v = g.view;
+  const uint64_t ld = static_cast<uint64_t>(v.radon_ld);
+  int lg = 0;
+  while ((uint64_t{1} << lg) < ld) ++lg;
+  const int sh = 32 + lg;
+  const uint64_t m = ((uint64_t{1} << sh) + ld - 1) / ld;
+  std::map<int, std::pair<uint32_t, float>> pair;
+  for (const BandLists* L : {&spread, &own})
+    for (const PointEntry& e : L->e) {
+      const uint64_t row = e.idx / ld;
+      CHECK(((static_cast<uint64_t>(e.idx) * m) >> sh) == row,
+            "%s: index %u: multiply-shift row differs", what, e.idx);
+      const int l = static_cast<int>(row) - v.radon_row0;
+      CHECK(l >= 0 && l < g.d.nq, "%s: index %u outside the plan's slownesses", what, e.idx);
+      auto it = pair.find(l);
+      if (it == pair.end()) {
+        pair[l] = {e.xq, e.w};
+      } else {
+        CHECK(it->second.first == e.xq && it->second.second == e.w,
+              "%s: slowness %d: entries disagree on angle or weight", what, l);
+      }
+    }
+}
+
 static void run(const char* name, const hrt_desc& d, const PartView* view) {
   Geometry g;
   std::string err;
@@ -135,6 +167,7 @@ static void run(const char* name, const hrt_desc& d, const PartView* view) {
   std::string a = std::string(name) + " data", b = std::string(name) + " radon";
   check_set(g, t.data_spread, t.data_own, data, a.c_str());
   check_set(g, t.radon_spread, t.radon_own, radon, b.c_str());
+  check_radon_slowness(g, t.radon_spread, t.radon_own, b.c_str());
   if (!(t.cmax_data > 0 && t.cmax_radon > 0)) {
     std::printf("%s: cmax\n", name);
     ++fails;
