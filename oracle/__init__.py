@@ -23,5 +23,16 @@ zeta by quadrature), `ista` (soft-thresholding iterations of Section 3),
 (the transform cut into parts in time and slowness, Sections 4 and 5).
 All arithmetic is float64.  Readings of points where the paper is silent or
 garbled are stated in each function's docstring.
+
+Every function is pinned by a test against something other than itself
+(tests/test_oracle_*.py): closed forms, invariants, brute force on tiny grids
+or an independent computation, each chosen so that a plausible slip fails
+it.  The kernel multiplier's B-spline division along each axis is pinned by
+a narrow Gaussian's closed form on the C2 grid, and the trapezoid end
+weights of the smear weight (first and last trace, last time sample) by the
+lattice mass against an adaptive quadrature and by a Gaussian on the last
+trace against direct summation.  Quantities with no paper value to check
+against (reconstruction SNR of the iterations, the quality of multiple
+attenuation) are reported, not pinned.
 """
 from . import bspline, geometry, kernel, logpolar, direct, ista, demultiple, split  # noqa: F401

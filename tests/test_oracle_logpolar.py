@@ -74,6 +74,89 @@ def test_log_polar_agrees_with_direct_sum_on_band_limited_data(op_c1):
     assert rel(op_c1.forward(f), direct.forward(d, f)) < 1e-3
 
 
+def test_kernel_deconvolution_pinned_by_narrow_gaussian():
+    """Section 2.2, eqs. d and B3tauq: the kernel multiplier divides the
+    kernel spectrum by the squared B-spline transform along each axis (once
+    for the smearing, once for the interpolation).  A narrow Gaussian in
+    (s, y) on the C2 grid carries enough high lattice frequencies that the
+    whole chain matches its closed form to 1e-5 only with both divisions
+    right: measured 3.1e-6 here; dividing by b instead of b^2 along the angle
+    axis gives 6.3e-5, along the log radius 5.2e-4."""
+    d = synth.config_desc("c2")
+    op = logpolar.LogPolarOracle(d)
+    f = synth.gaussian_sy_gather(d, 0.6, 0.3, 0.015)
+    exact = gaussian_exact(op.geo, 0.6, 0.3, 0.015)
+    assert rel(op.forward(f), exact) < 1e-5
+
+
+def test_log_polar_agrees_with_direct_sum_at_the_last_trace(op_c1):
+    """Section 2.2, eq. B3tx2 (trapezoid rule in offset): a smooth Gaussian
+    in (s, y) centred on the last trace (y = 1) is cut by the record's edge,
+    where the trapezoid weight 1/2 of the last trace decides the sum.  The
+    method agrees with direct summation to 1e-3 (measured 5.9e-4); a weight of
+    1 on the last trace (or on both end traces) gives 4.6e-2."""
+    d = op_c1.desc
+    f = synth.gaussian_sy_gather(d, 0.6, 0.95, 0.05)
+    assert rel(op_c1.forward(f), direct.forward(d, f)) < 1e-3
+
+
+def _ramp(z):
+    """C-infinity step: 0 for z <= 0, 1 for z >= 1."""
+    z = np.clip(z, 1e-9, 1.0 - 1e-9)
+    a = np.exp(-1.0 / z)
+    b = np.exp(-1.0 / (1.0 - z))
+    return a / (a + b)
+
+
+def _mass_test_data(th, xh, k, m=0.05, width=0.15):
+    """Smooth data that vanish near the trapezoid's slanted edge t^ = k x^
+    and not at the other three edges x^ = 0, x^ = 1, t^ = 1."""
+    u = (th - k * xh - m) / width
+    h = np.where(u <= 0.0, 0.0, np.where(u >= 1.0, 1.0, _ramp(u)))
+    return h * (1.0 + 0.5 * xh + 0.3 * th)
+
+
+def test_lattice_mass_is_the_trapezoid_quadrature(op_c1):
+    """Section 2.2, eq. B3tx2: the smear weights are a quadrature of the
+    polar-coordinate integral of eq. lpfwd.  B-splines form a partition of
+    unity, so the lattice's total mass after the spread is sum_p W_p f_p; for
+    smooth data it must approximate, with the second-order error of the
+    trapezoid rule, the integral of f~(s, y) e^(-rho) over the plane of the
+    square (f~ = f / (2 sqrt y), eq. f; e^(-rho) = 1/|p|; dp = a^2 ds dy
+    because T is a rotation scaled by a), evaluated here by adaptive
+    quadrature in (s, y).  Measured 2.8e-6 relative.  Planted in the weights:
+    weight 1 on the first trace (x = 0) 3.5e-3, on the last trace 4.0e-3, on
+    the last time sample 4.2e-3."""
+    from scipy import integrate
+
+    d = op_c1.desc
+    g = op_c1.geo
+    k = g.qhat[0]
+    th = np.arange(d.nt) * d.dt / g.T
+    xh = (d.x0 + np.arange(d.nx) * d.dx) / g.X
+    f = _mass_test_data(th[None, :], xh[:, None], k)
+    M1, M2 = op_c1.lattice_shape
+    mass = logpolar.spread(op_c1.d_x, op_c1.d_y, op_c1.d_w * f[op_c1.kept], M1, M2).sum()
+
+    def inner(y):
+        xs = math.sqrt(y)
+
+        def fs(s):
+            u, v = geometry.map_T(np.array(s), np.array(y), g.alpha, g.a, g.O1, g.O2)
+            return float(_mass_test_data(math.sqrt(s), xs, k)) * g.a ** 2 / math.hypot(float(u), float(v))
+
+        s_lo = (k * xs + 0.05) ** 2
+        s_mid = min(1.0, (k * xs + 0.2) ** 2)
+        val = integrate.quad(fs, s_lo, s_mid, epsabs=0, epsrel=1e-12, limit=200)[0]
+        if s_mid < 1.0:
+            val += integrate.quad(fs, s_mid, 1.0, epsabs=0, epsrel=1e-12, limit=200)[0]
+        return 0.5 * val  # f~ = f / (2 sqrt y); the 1/sqrt(y) is quad's weight
+
+    exact = integrate.quad(inner, 0.0, 1.0, weight="alg", wvar=(-0.5, 0.0),
+                           epsabs=0, epsrel=1e-11, limit=200)[0]
+    assert abs(mass - exact) / exact < 1e-4
+
+
 def test_single_event_focuses(op_c1):
     """A hyperbolic event with (tau0, q0) on grid nodes focuses there."""
     d = op_c1.desc
