@@ -121,6 +121,22 @@ hrt_status hrt_forward(hrt_plan_t plan, const float* f, float* g,
 hrt_status hrt_adjoint(hrt_plan_t plan, const float* g, float* f,
                        void* stream);
 
+/* hrt_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result, bit for bit, as hrt_forward, but
+ * the per-call workspace (half spectrum, spread partial rows, real lattice
+ * rows, input maxima) is taken from a fixed 64 MiB array in device memory
+ * that each GPU the library runs on holds until the process ends, instead
+ * of the plan's own.  It calls no allocator.  Every call on one GPU shares
+ * that GPU's array, so calls that overlap on a GPU (concurrent streams,
+ * threads) race and must be serialised by the caller; a call leaves its
+ * workspace contents behind, and no call depends on what an earlier one
+ * left.  Same arrays and stream rules as hrt_forward.  Returns
+ * HRT_ERR_UNSUPPORTED, before any launch, for a plan whose forward
+ * workspace exceeds 64 MiB (the C3 grid, 2048 x 1024 -> 2048 x 1024, needs
+ * about 47 MB). */
+hrt_status hrt_forward_noalloc(hrt_plan_t plan, const float* f, float* g, void* stream);
+
 /* Normal operator: g = R_h f, then fa = R_h^T g (the forward followed by the
  * adjoint of its output, as in the power iteration for ||R_h||^2 and in the
  * iterative schemes of Section 3, which apply both operators in turn).

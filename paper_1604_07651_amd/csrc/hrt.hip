@@ -284,6 +284,53 @@ std::mutex g_attr_mu;
 
 }  // namespace
 
+// Per-call workspace of hrt_forward_noalloc: a fixed array in device memory
+// that every GPU the library runs on holds until the process ends.  In host
+// code the name `scratch` is only a stand-in for the symbol; its device
+// address comes from hipGetSymbolAddress, taken once per device (with that
+// device current) when the first plan is created there.
+constexpr size_t kStaticScratchBytes = size_t{64} << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's scratch array (the device current).
+hrt_status static_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return set_err(HRT_ERR_UNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return hip_err(e == hipSuccess ? hipErrorInvalidSymbol : e, "hipGetSymbolAddress(scratch)");
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HRT_OK;
+}
+
+// Where one forward's workspace (half spectrum, spread partial rows, real
+// rows, input maxima) sits in the scratch array: 256-byte aligned pieces.
+struct ScratchLayout {
+  size_t S = 0, Hp = 0, Cr = 0, absmax = 0, total = 0;
+};
+ScratchLayout scratch_layout(const Geometry& g, int spread_chunks) {
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  ScratchLayout L;
+  L.S = 0;
+  L.Hp = L.S + up(static_cast<size_t>(g.K1) * g.Mr * sizeof(float2));
+  L.Cr = L.Hp + up(static_cast<size_t>(spread_chunks) * g.R * g.W * sizeof(int));
+  L.absmax = L.Cr + up(static_cast<size_t>(g.u1 - g.u0) * g.W * sizeof(float));
+  L.total = L.absmax + up(kAbsMaxBlocks * sizeof(float));
+  return L;
+}
+}  // namespace
+
 extern "C" {
 
 const char* hrt_status_string(hrt_status s) {
@@ -326,6 +373,11 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
   // the band kernels also hold twiddles and reduction slots in static LDS
   const int64_t lds = std::min<int64_t>(lds_max, 163840) - kBandStaticLds;
   (void)hipGetLastError();  // do not report an earlier, unrelated error
+  {
+    void* sp = nullptr;  // this device's scratch address, taken once
+    hrt_status ss = static_scratch(dev, &sp);
+    if (ss != HRT_OK) return ss;
+  }
 
   auto* p = new hrt_plan_s();
   p->magic = kMagic;
@@ -663,10 +715,10 @@ struct StageTimer {
 // input uses them instead of launching its own input maximum (five
 // launches).
 static void run_chain(hrt_plan_t p, const float* in, float* out, hipStream_t st, bool adjoint,
-                      bool accumulate, bool chained = false) {
+                      bool accumulate, bool chained = false, const DevGeo* ws = nullptr) {
   const Geometry& g = p->g;
   const size_t sb = g.spread_bytes, rb = g.row_bytes, cb = g.col_bytes, gb = g.gather_bytes;
-  DevGeo G = p->dg;
+  DevGeo G = ws ? *ws : p->dg;
   G.accumulate = accumulate ? 1 : 0;
   if (chained && !adjoint) G.gmax = p->gmax;
   if (chained && adjoint) {
@@ -734,6 +786,37 @@ hrt_status hrt_forward(hrt_plan_t p, const float* f, float* g, void* stream) {
 
 hrt_status hrt_adjoint(hrt_plan_t p, const float* g, float* f, void* stream) {
   return launch_chain(p, g, f, stream, true);
+}
+
+hrt_status hrt_forward_noalloc(hrt_plan_t p, const float* f, float* g, void* stream) {
+  hrt_status s = check_plan(p);
+  if (s != HRT_OK) return s;
+  if (!f || !g) return set_err(HRT_ERR_INVALID_ARG, "null array");
+  const size_t nd = static_cast<size_t>(p->g.d.nx) * p->g.d.nt * sizeof(float);
+  const size_t nr = static_cast<size_t>(p->g.d.nq) * p->g.d.ntau * sizeof(float);
+  const char* fb = reinterpret_cast<const char*>(f);
+  const char* gb = reinterpret_cast<const char*>(g);
+  if (fb < gb + nr && gb < fb + nd) return set_err(HRT_ERR_INVALID_ARG, "input and output overlap");
+  const ScratchLayout L = scratch_layout(p->g, p->nchunks[kDataSpread]);
+  if (L.total > kStaticScratchBytes)
+    return set_err(HRT_ERR_UNSUPPORTED,
+                   "the plan's forward workspace (" + std::to_string(L.total) +
+                       " bytes) exceeds the static workspace of hrt_forward_noalloc (" +
+                       std::to_string(kStaticScratchBytes) + " bytes)");
+  DeviceGuard guard(p->device);
+  void* base = nullptr;
+  if ((s = static_scratch(p->device, &base)) != HRT_OK) return s;
+  unsigned char* b = static_cast<unsigned char*>(base);
+  DevGeo G = p->dg;
+  G.S = reinterpret_cast<float2*>(b + L.S);
+  G.Hp = reinterpret_cast<int*>(b + L.Hp);
+  G.Cr = reinterpret_cast<float*>(b + L.Cr);
+  G.absmax = reinterpret_cast<float*>(b + L.absmax);
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
+  run_chain(p, f, g, reinterpret_cast<hipStream_t>(stream), false, false, false, &G);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_err(e, "forward launch");
+  return HRT_OK;
 }
 
 namespace {

@@ -85,6 +85,12 @@ class Plan:
         return self._call(self._lib.hrt_forward, f, out, self.data_shape,
                           self.radon_shape, stream, "hrt_forward")
 
+    def forward_noalloc(self, f: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """hrt_forward_noalloc: g = R_h f with the library's static per-device
+        workspace instead of the plan's (the caller provides `out`)."""
+        return self._call(self._lib.hrt_forward_noalloc, f, out, self.data_shape,
+                          self.radon_shape, stream, "hrt_forward_noalloc")
+
     def adjoint(self, g: torch.Tensor, out=None, stream=None) -> torch.Tensor:
         """f = R_h^T g: g (nq, ntau) -> f (nx, nt)."""
         return self._call(self._lib.hrt_adjoint, g, out, self.radon_shape,
