@@ -25,6 +25,10 @@ struct DevList {
   const int64_t* chunk_off;
   const int* chunk_band;
   const int* band_chunk;
+  // spread lists: the window columns {c_lo, wc} of each chunk and where its
+  // partial rows (R x wc floats) start in Hp; null for the owned lists
+  const int2* chunk_col;
+  const int64_t* chunk_hp;
   int nchunks;
 };
 
@@ -37,6 +41,7 @@ struct DevGeo {
   int row_rows, row_sub_shift;  // rows of a row-FFT item, log2 items per band
   int xw0, W;         // angle columns [xw0, xw0 + W) that points can touch
   int x_frac_bits;    // fraction bits of the angle coordinate of a point entry
+  int spread_cols;    // most columns of a spread chunk (its LDS accumulator)
   // row FFTs: sequences per group, byte offset of the LDS scratch (-1: in
   // place); the column FFT in place or not
   int row_group, row_scratch;
@@ -56,7 +61,7 @@ struct DevGeo {
   const float2* tw_r;
   const float2* K;              // kernel multiplier [K1][K2]
   float2* S;                    // half spectrum [K1][Mr]
-  int* Hp;                      // spread partial rows [chunk][R][W]
+  float* Hp;                    // spread partial rows, chunk c's R x wc at chunk_hp[c]
   float* Cr;                    // real rows after the inverse row FFT [u1-u0][W]
   float* absmax;                // absmax_blocks partial maxima
   // when set, the forward gather stores the largest |output| of each of its
@@ -65,7 +70,8 @@ struct DevGeo {
   float* gmax;
   // per slowness of the plan: {angle coordinate, weight bits} of its Radon
   // points; a Radon sample index idx lies in array row
-  // (idx * rdiv_m) >> rdiv_s = idx / radon_ld (exact for idx < 2^32)
+  // (idx * rdiv_m) >> rdiv_s = idx / radon_ld (exact for idx < 2^31, which
+  // plans enforce; the plan also checks it for every entry)
   const uint2* q_tab;
   uint64_t rdiv_m;
   int rdiv_s;

@@ -7,8 +7,11 @@
 // stored column-major as S[k1][row].  Point coordinates are placed once per
 // plan in float64 on the host (eqs. transformT, transformP; the Radon side
 // e^rho = A_l + B_l tau^2) and kept on the device as per-band lists of
-// 16-byte entries; everything on the lattice is float32 with float32
-// accumulation, except the spread, which sums in 64-bit fixed point.
+// entries of 16 bytes (data) or 8 bytes (Radon, the angle coordinate and
+// weight coming from a per-slowness table); everything on the lattice is
+// float32 with float32 accumulation, except inside one chunk of the
+// spread, whose float32 taps are summed exactly in 64-bit fixed point and
+// rounded once to float32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -75,8 +78,11 @@ struct hrt_plan_s {
   int64_t* chunk_off[4] = {};
   int* chunk_band[4] = {};
   int* band_chunk[4] = {};
+  int2* chunk_col[4] = {};       // spread lists: columns {c_lo, wc} of each chunk
+  int64_t* chunk_hp[4] = {};     // spread lists: start of each chunk's partial rows
+  int64_t hp_floats[4] = {};     // spread lists: floats of all partial rows
   int nchunks[4] = {};
-  int* Hp = nullptr;        // partial fixed-point rows of the spread chunks
+  float* Hp = nullptr;      // partial rows of the spread chunks (float32)
   float* Cr = nullptr;      // real lattice rows after the inverse row FFT
   float* absmax = nullptr;  // kAbsMaxBlocks partial maxima of the current input
   float* gmax = nullptr;    // partial maxima of the forward's output, one per gather chunk
@@ -194,7 +200,7 @@ void free_plan(hrt_plan_s* p) {
     if (q) (void)hipFree(q);
   for (int i = 0; i < 4; ++i) {
     void* lists[] = {p->ent[i], p->ent2[i], p->chunk_off[i], p->chunk_band[i],
-                     p->band_chunk[i]};
+                     p->band_chunk[i], p->chunk_col[i], p->chunk_hp[i]};
     for (void* q : lists)
       if (q) (void)hipFree(q);
   }
@@ -319,12 +325,12 @@ hrt_status static_scratch(int dev, void** out) {
 struct ScratchLayout {
   size_t S = 0, Hp = 0, Cr = 0, absmax = 0, total = 0;
 };
-ScratchLayout scratch_layout(const Geometry& g, int spread_chunks) {
+ScratchLayout scratch_layout(const Geometry& g, int64_t hp_floats) {
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
   ScratchLayout L;
   L.S = 0;
   L.Hp = L.S + up(static_cast<size_t>(g.K1) * g.Mr * sizeof(float2));
-  L.Cr = L.Hp + up(static_cast<size_t>(spread_chunks) * g.R * g.W * sizeof(int));
+  L.Cr = L.Hp + up(static_cast<size_t>(hp_floats) * sizeof(float));
   L.absmax = L.Cr + up(static_cast<size_t>(g.u1 - g.u0) * g.W * sizeof(float));
   L.total = L.absmax + up(kAbsMaxBlocks * sizeof(float));
   return L;
@@ -478,6 +484,19 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
         delete p;
         return s;
       }
+      if (i == kDataSpread || i == kRadonSpread) {
+        p->hp_floats[i] = L.hp_floats;
+        std::vector<int2> cols(L.chunk_band.size());
+        for (size_t c = 0; c < cols.size(); ++c)
+          cols[c] = make_int2(L.chunk_col[2 * c], L.chunk_col[2 * c + 1]);
+        if ((s = dev_alloc(&p->chunk_col[i], cols.size(), total)) ||
+            (s = dev_alloc(&p->chunk_hp[i], L.chunk_hp.size(), total)) ||
+            (s = upload(p->chunk_col[i], cols)) || (s = upload(p->chunk_hp[i], L.chunk_hp))) {
+          free_plan(p);
+          delete p;
+          return s;
+        }
+      }
       if (!radon && !L.e.empty()) {
         hipError_t e = hipMemcpy(p->ent[i], L.e.data(), L.e.size() * sizeof(PointEntry),
                                  hipMemcpyHostToDevice);
@@ -493,10 +512,11 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
       delete p;
       return s;
     }
-    // one partial per spread chunk, and the real rows after the inverse FFT
-    const size_t parts = static_cast<size_t>(
-        std::max(p->nchunks[kDataSpread], p->nchunks[kRadonSpread]));
-    if ((s = dev_alloc(&p->Hp, parts * g.R * g.W, total)) ||
+    // the partial rows of the spread chunks (of whichever direction needs
+    // more), and the real rows after the inverse FFT
+    const size_t parts = static_cast<size_t>(std::max<int64_t>(
+        1, std::max(p->hp_floats[kDataSpread], p->hp_floats[kRadonSpread])));
+    if ((s = dev_alloc(&p->Hp, parts, total)) ||
         (s = dev_alloc(&p->Cr, static_cast<size_t>(g.u1 - g.u0) * g.W, total)) ||
         (s = dev_alloc(&p->gmax, static_cast<size_t>(p->nchunks[kRadonOwn]), total))) {
       free_plan(p);
@@ -582,7 +602,7 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
   G.Mt = g.Mt; G.Mr = g.Mr; G.K1 = g.K1; G.K2 = g.K2; G.u0 = g.u0; G.u1 = g.u1;
   G.R = g.R; G.nbands = g.nbands;
   G.row_rows = g.row_rows; G.row_sub_shift = g.row_sub_shift;
-  G.xw0 = g.xw0; G.W = g.W; G.x_frac_bits = g.x_frac_bits;
+  G.xw0 = g.xw0; G.W = g.W; G.x_frac_bits = g.x_frac_bits; G.spread_cols = g.spread_cols;
   G.row_group = g.row_group; G.row_scratch = g.row_scratch;
   G.col_inplace = g.inplace_col ? 1 : 0;
   G.col_batch = g.col_batch;
@@ -608,7 +628,7 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
   G.rdiv_s = p->rdiv_s;
   for (int i = 0; i < 4; ++i)
     G.lists[i] = DevList{p->ent[i], p->ent2[i], p->chunk_off[i], p->chunk_band[i],
-                         p->band_chunk[i], p->nchunks[i]};
+                         p->band_chunk[i], p->chunk_col[i], p->chunk_hp[i], p->nchunks[i]};
   {
     // the descriptor and the single-gather work lists on the device
     std::vector<int2> it[kItemSets];
@@ -797,7 +817,7 @@ hrt_status hrt_forward_noalloc(hrt_plan_t p, const float* f, float* g, void* str
   const char* fb = reinterpret_cast<const char*>(f);
   const char* gb = reinterpret_cast<const char*>(g);
   if (fb < gb + nr && gb < fb + nd) return set_err(HRT_ERR_INVALID_ARG, "input and output overlap");
-  const ScratchLayout L = scratch_layout(p->g, p->nchunks[kDataSpread]);
+  const ScratchLayout L = scratch_layout(p->g, p->hp_floats[kDataSpread]);
   if (L.total > kStaticScratchBytes)
     return set_err(HRT_ERR_UNSUPPORTED,
                    "the plan's forward workspace (" + std::to_string(L.total) +
@@ -809,7 +829,7 @@ hrt_status hrt_forward_noalloc(hrt_plan_t p, const float* f, float* g, void* str
   unsigned char* b = static_cast<unsigned char*>(base);
   DevGeo G = p->dg;
   G.S = reinterpret_cast<float2*>(b + L.S);
-  G.Hp = reinterpret_cast<int*>(b + L.Hp);
+  G.Hp = reinterpret_cast<float*>(b + L.Hp);
   G.Cr = reinterpret_cast<float*>(b + L.Cr);
   G.absmax = reinterpret_cast<float*>(b + L.absmax);
   (void)hipGetLastError();  // do not report an earlier, unrelated error
@@ -851,15 +871,18 @@ hrt_status hrt_ista_iterate(hrt_plan_t p, const float* f, const float* mask, flo
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int64_t n_data = static_cast<int64_t>(p->g.d.nx) * p->g.d.nt;
   const int64_t n_radon = static_cast<int64_t>(p->g.d.nq) * p->g.d.ntau;
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
   for (int it = 0; it < iters; ++it) {
-    if ((s = launch_chain(p, g, work_data, stream, true)) != HRT_OK) return s;
+    // the arrays were checked above; every launch of the iteration,
+    // the element-wise ones included, is checked after it
+    run_chain(p, g, work_data, st, true, false);
     k_residual<<<vec_blocks(n_data), kVecThreads, 0, st>>>(f, mask, work_data, n_data);
-    if ((s = launch_chain(p, work_data, work_radon, stream, false)) != HRT_OK) return s;
+    run_chain(p, work_data, work_radon, st, false, false);
     k_soft_update<<<vec_blocks(n_radon), kVecThreads, 0, st>>>(g, work_radon, c2,
                                                                0.5f * c2 * mu, n_radon);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_err(e, "ista launch");
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_err(e, "ista launch");
   return HRT_OK;
 }
 
@@ -982,8 +1005,10 @@ hrt_status hrt_opnorm2(hrt_plan_t p, int32_t iters, uint64_t seed, float* work_d
   }
   HRT_HIP(hipMemcpyAsync(work_data, v0.data(), nd, hipMemcpyHostToDevice, st), "upload start");
   std::vector<double> part(kDotBlocks);
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
   auto dot = [&](const float* a, const float* b, double& r) -> hrt_status {
     k_dot64<<<kDotBlocks, kVecThreads, 0, st>>>(a, b, n_data, p->dot);
+    HRT_HIP(hipGetLastError(), "power iteration dot launch");
     HRT_HIP(hipMemcpyAsync(part.data(), p->dot, kDotBlocks * sizeof(double),
                            hipMemcpyDeviceToHost, st),
             "read partial sums");
@@ -996,6 +1021,7 @@ hrt_status hrt_opnorm2(hrt_plan_t p, int32_t iters, uint64_t seed, float* work_d
   if ((s = dot(work_data, work_data, vv)) != HRT_OK) return s;
   k_scale<<<vec_blocks(n_data), kVecThreads, 0, st>>>(work_data, work_data, 1.0 / std::sqrt(vv),
                                                        n_data);
+  HRT_HIP(hipGetLastError(), "power iteration scale launch");
   for (int it = 0; it < iters; ++it) {
     // w = R* R v, lambda = <v, w> for |v| = 1, then v = w / |w|
     if ((s = hrt_normal(p, work_data, work_radon, work_data2, stream)) != HRT_OK) return s;
@@ -1006,6 +1032,7 @@ hrt_status hrt_opnorm2(hrt_plan_t p, int32_t iters, uint64_t seed, float* work_d
     if (!(ww > 0.0)) break;
     k_scale<<<vec_blocks(n_data), kVecThreads, 0, st>>>(work_data, work_data2,
                                                          1.0 / std::sqrt(ww), n_data);
+    HRT_HIP(hipGetLastError(), "power iteration scale launch");
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, "power iteration");
@@ -1027,8 +1054,10 @@ hrt_status hrt_demultiple(hrt_plan_t p, const float* f, const float* g, double q
     return set_err(HRT_ERR_INVALID_ARG, "arrays overlap");
   DeviceGuard guard(p->device);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
   k_mute_multiples<<<vec_blocks(n_radon), kVecThreads, 0, st>>>(
       g, work_radon, d.ntau, d.nq, d.tau0, d.dtau, d.q0, d.dq, qb0, qb_slope);
+  HRT_HIP(hipGetLastError(), "demultiple mute launch");
   if ((s = launch_chain(p, work_radon, out, stream, true)) != HRT_OK) return s;
   k_residual<<<vec_blocks(n_data), kVecThreads, 0, st>>>(f, nullptr, out, n_data);
   hipError_t e = hipGetLastError();

@@ -11,9 +11,11 @@
 //   k_absmax   largest |input| (fixes the spread's fixed-point scale)
 //   k_spread   one workgroup per chunk of a band's spread list: smear the
 //              chunk's samples (data samples for the forward, Radon samples
-//              for the adjoint) onto the band's rows in LDS, store the rows
-//              (32-bit fixed point) as the chunk's partial Hp[chunk]
-//   k_rowfft   one workgroup per band: sum the band's partials, FFT along
+//              for the adjoint) onto the band's rows over the columns the
+//              chunk spans, in LDS (exact 64-bit fixed-point sums); store
+//              them rounded to float32 as the chunk's partial rows
+//   k_rowfft   one workgroup per band: sum the band's partials (float32, in
+//              chunk order), FFT along
 //              the angle, two real rows per complex sequence; store k1 < K1
 //              of the half spectrum, column-major S[k1][row]
 //   k_colfft   one workgroup per kept k1: FFT along the log radius, multiply
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(256) void k_absmax(DevGeo one, const DevGeo* __rest
     G.absmax[w.i] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
 }
 
-// The spread's fixed-point scale: every accumulated cell stays within 2^30
+// The spread's fixed-point scale: every accumulated cell stays within 2^61
 // (cmax bounds a cell per unit of input); 0 for an all-zero or non-finite
 // input (the latter is reported through `finite`).
 __device__ __forceinline__ float spread_scale(const DevGeo& G, float cmax, float* s_wave,
@@ -115,20 +117,27 @@ __device__ __forceinline__ float spread_scale(const DevGeo& G, float cmax, float
   for (int i = threadIdx.x; i < G.absmax_blocks; i += kNtBand) vmax = fmaxf(vmax, G.absmax[i]);
   vmax = block_max(vmax, s_wave);
   finite = vmax <= 3.0e38f;  // false for inf and NaN
-  return (vmax > 0.0f && finite) ? 1073741824.0f / (cmax * vmax) : 0.0f;
+  // 2^61 / (cmax vmax), formed in float64 so that neither factor can
+  // overflow float32 on the way
+  return (vmax > 0.0f && finite)
+             ? static_cast<float>(2305843009213693952.0 / (static_cast<double>(cmax) * vmax))
+             : 0.0f;
 }
 
 // Spread of one chunk (MODE 0: data samples of f[nx][nt]; MODE 1: Radon
 // samples of g[nq][ntau]); item i is chunk i of the spread list.  Dynamic
-// LDS: the band's R x W fixed-point rows, then a staging buffer for
-// kSpreadStage entries.  The chunk's entries are read coalesced into the
-// staging buffer; thread s then takes a contiguous segment of it, segments
-// dealt so that the lanes of a wave work far apart on the lattice.
+// LDS: the band's R rows over the chunk's wc columns [c_lo, c_lo + wc) as
+// 64-bit fixed-point cells (R x spread_cols reserved), then a staging
+// buffer for kSpreadStage entries.  The chunk's entries are read coalesced
+// into the staging buffer; thread s then takes a contiguous segment of it,
+// segments dealt so that the lanes of a wave work far apart on the lattice.
+// The chunk's exact sums are rounded once to float32 into its partial rows,
+// R x wc floats at Hp + chunk_hp[chunk].
 template <int MODE, bool BATCH>
 __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __restrict__ geos,
                                                     const int2* __restrict__ items,
                                                     const float* __restrict__ in_base) {
-  extern __shared__ int lds_i[];
+  extern __shared__ unsigned long long lds_q[];
   __shared__ float s_wave[kNtBand / 64];
   const Work w = work_item<BATCH>(one, geos, items);
   if (w.i < 0) return;  // a gap in the XCD-ordered items
@@ -139,12 +148,13 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
   const int band = L.chunk_band[chunk];
   const int n0 = G.u0 + band * G.R;
   const int nr = min(G.R, G.u1 - n0);
-  const int W = G.W;
-  int* acc = lds_i;
-  uint4* stage = reinterpret_cast<uint4*>(lds_i + G.R * W);
+  const int2 cols = L.chunk_col[chunk];  // {c_lo, wc}
+  const int wc = cols.y;
+  unsigned long long* acc = lds_q;
+  uint4* stage = reinterpret_cast<uint4*>(lds_q + G.R * G.spread_cols);
   bool finite;
   const float scale = spread_scale(G, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave, finite);
-  for (int i = threadIdx.x; i < nr * W; i += kNtBand) acc[i] = 0;
+  for (int i = threadIdx.x; i < nr * wc; i += kNtBand) acc[i] = 0ull;
   __syncthreads();
   if (scale > 0.0f) {
     const int64_t e0 = L.chunk_off[chunk], e1 = L.chunk_off[chunk + 1];
@@ -182,16 +192,19 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
         for (int t = 0; t < 4; ++t) {
           if (v[t] != 0.0f) {
             const EntryTaps tp = decode_entry(E[t].y, E[t].z, G.x_frac_bits);
-            spread_taps(acc, W, nr, tp, v[t] * __uint_as_float(E[t].w) * scale);
+            spread_taps(acc, wc, cols.x, nr, tp, v[t] * __uint_as_float(E[t].w) * scale);
           }
         }
       }
       __syncthreads();
     }
   }
-  // the chunk's partial rows, R x W (rows past nr unused)
-  int* dst = G.Hp + static_cast<size_t>(chunk) * G.R * W;
-  for (int i = threadIdx.x; i < nr * W; i += kNtBand) dst[i] = acc[i];
+  // the chunk's partial rows, R x wc (rows past nr unused), each exact sum
+  // rounded to float32
+  const double inv = scale > 0.0f ? 1.0 / static_cast<double>(scale) : 0.0;
+  float* dst = G.Hp + L.chunk_hp[chunk];
+  for (int i = threadIdx.x; i < nr * wc; i += kNtBand)
+    dst[i] = static_cast<float>(static_cast<double>(static_cast<long long>(acc[i])) * inv);
 }
 
 static_assert(kMaxBandRows >= 2 && (kMaxBandRows & (kMaxBandRows - 1)) == 0,
@@ -206,8 +219,8 @@ __device__ __forceinline__ int pair_shift(int npair) {
 
 // Row FFT of row_rows rows of a band (item i: band i >> row_sub_shift, the
 // rows from (i mod 2^row_sub_shift) * row_rows on): the sum of the band's
-// chunks' partials of those rows,
-// fixed point to float (NaN everywhere for a non-finite input), rows
+// chunks' float32 partials of those rows, in chunk order (NaN everywhere
+// for a non-finite input), rows
 // (2p, 2p+1) into complex pair p, FFT along the angle, and the k1 < K1 half
 // spectrum of both rows to S.  Dynamic LDS: the pairs, then the FFT scratch
 // (if any).
@@ -230,34 +243,46 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
   const int npair = nr >> 1;
   const int Mt = G.Mt, W = G.W, SP = padded_len(G.Mt);
   bool finite;
-  const float scale = spread_scale(G, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave, finite);
-  const float inv = scale > 0.0f ? 1.0f / scale : 0.0f;
+  (void)spread_scale(G, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave, finite);
   const float bad = finite ? 0.0f : __int_as_float(0x7fc00000);
   const int q0 = L.band_chunk[band], q1 = L.band_chunk[band + 1];
   // angle columns outside the window hold no point: zero
   for (int p = 0; p < npair; ++p)
     for (int m = threadIdx.x; m < Mt; m += kNtBand)
       if (m < G.xw0 || m >= G.xw0 + W) lds[p * SP + lpad(m)] = make_float2(0.0f + bad, 0.0f + bad);
-  // the window: the item's 2 npair rows are one block of 2 npair W ints in
-  // every chunk's partial (W % 4 == 0, so a 16-byte group never crosses a
-  // row); exact integer sums over the band's chunks (two's complement, so
-  // order does not matter), kGroups 16-byte groups per thread in flight
-  // together for each chunk (clamped indices: a group past the end is
-  // loaded again and not stored)
+  // the window: the sum over the band's chunks, in chunk order, of their
+  // float32 partials; chunk q holds rows x columns [c_lo, c_lo + wc) of the
+  // band (c_lo, wc multiples of 4, so a 16-byte group never crosses a row
+  // or a chunk's edge).  Work unit j: row j / W4 of the item, columns
+  // 4 (j mod W4) .. +3; kGroups units per thread in flight together for
+  // each chunk.
   {
     constexpr int kGroups = 4;
-    const int n4 = npair * W / 2;  // 16-byte groups of the block
+    const int W4 = W >> 2;
+    const int n4 = 2 * npair * W4;
+    const unsigned m_w4 = div_magic(W4);
     float* ldsf = reinterpret_cast<float*>(lds);
     for (int j0 = threadIdx.x; j0 < n4; j0 += kNtBand * kGroups) {
-      int4 acc[kGroups];
+      float4 acc[kGroups];
+      int rr[kGroups], cc[kGroups];
 #pragma unroll
-      for (int g = 0; g < kGroups; ++g) acc[g] = make_int4(0, 0, 0, 0);
+      for (int g = 0; g < kGroups; ++g) {
+        acc[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int j = j0 + g * kNtBand;
+        rr[g] = div_small(j, m_w4);
+        cc[g] = 4 * (j - rr[g] * W4);
+      }
       for (int q = q0; q < q1; ++q) {
-        const int4* part =
-            reinterpret_cast<const int4*>(G.Hp + (static_cast<size_t>(q) * G.R + r0) * W);
-        int4 v[kGroups];
+        const int2 cq = L.chunk_col[q];
+        const float* part = G.Hp + L.chunk_hp[q] + static_cast<size_t>(r0) * cq.y;
+        float4 v[kGroups];
 #pragma unroll
-        for (int g = 0; g < kGroups; ++g) v[g] = part[min(j0 + g * kNtBand, n4 - 1)];
+        for (int g = 0; g < kGroups; ++g) {
+          const int c = cc[g] - cq.x;
+          v[g] = (j0 + g * kNtBand < n4 && c >= 0 && c < cq.y)
+                     ? *reinterpret_cast<const float4*>(part + rr[g] * cq.y + c)
+                     : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
 #pragma unroll
         for (int g = 0; g < kGroups; ++g) {
           acc[g].x += v[g].x;
@@ -268,15 +293,12 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
       }
 #pragma unroll
       for (int g = 0; g < kGroups; ++g) {
-        const int j = j0 + g * kNtBand;
-        if (j < n4) {
-          const int r = (4 * j) / W;       // row of the item
-          const int c = 4 * j - r * W;     // first window column of the group
+        if (j0 + g * kNtBand < n4) {
+          const int r = rr[g];
           float* dst = ldsf + 2 * ((r >> 1) * SP) + (r & 1);
-          const int a[4] = {acc[g].x, acc[g].y, acc[g].z, acc[g].w};
+          const float a[4] = {acc[g].x, acc[g].y, acc[g].z, acc[g].w};
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
-            dst[2 * lpad(G.xw0 + c + t)] = static_cast<float>(a[t]) * inv + bad;
+          for (int t = 0; t < 4; ++t) dst[2 * lpad(G.xw0 + cc[g] + t)] = a[t] + bad;
         }
       }
     }

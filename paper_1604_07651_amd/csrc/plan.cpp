@@ -418,14 +418,22 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
       if (fft_fits_inplace(g.fft_t, b, kBandThreads, kInplaceValues)) grp = b;
     return grp;
   };
+  // columns a spread chunk may span: its 64-bit accumulator of R rows and
+  // the staging buffer fill kSpreadLds (at most the whole window)
+  auto spread_cols = [&](int R) {
+    const int64_t c = (int64_t{kSpreadLds} - int64_t{kSpreadStage} * 16) / (int64_t{R} * 8);
+    return static_cast<int>(std::min<int64_t>(g.W, c & ~int64_t{3}));
+  };
   auto layout = [&](int R, bool commit) {
-    const int64_t spread = static_cast<int64_t>(R) * g.W * 4 + int64_t{kSpreadStage} * 16;
+    const int64_t spread =
+        static_cast<int64_t>(R) * spread_cols(R) * 8 + int64_t{kSpreadStage} * 16;
     const int rr = std::min(R, kRowRows);  // rows of a row-FFT item
     const int grp = inplace_group(rr / 2);
     const int64_t pairs = (rr / 2) * seq;
     const int64_t row = pairs + (grp ? 0 : pairs);
     const int64_t gather = static_cast<int64_t>(R + 3) * g.W * 4;
     if (commit) {
+      g.spread_cols = spread_cols(R);
       g.spread_bytes = static_cast<int>(spread);
       g.row_bytes = static_cast<int>(row);
       g.gather_bytes = static_cast<int>(gather);
@@ -440,11 +448,8 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   // band heights 2, 4, 8, ...: a band holds a power-of-two number of row
   // pairs, and the last band an even number of rows not above it
   g.R = kMaxBandRows;
-  while (g.R > 4 && static_cast<int64_t>(g.R) * g.W * 4 + int64_t{kSpreadStage} * 16 >
-                        kBandLdsPreferred)
-    g.R /= 2;
   while (g.R > 2 && layout(g.R, false) > lds_bytes) g.R /= 2;
-  if (layout(g.R, false) > lds_bytes)
+  if (layout(g.R, false) > lds_bytes || spread_cols(g.R) < 8)
     return fail(err, HRT_ERR_UNSUPPORTED, "angle axis too long for the LDS row bands");
   layout(g.R, true);
   // one column per workgroup by default: two per workgroup (fewer, fuller
@@ -502,6 +507,59 @@ void make_chunks(int nb, int max_entries, BandLists& L) {
   }
   L.band_chunk[nb] = static_cast<int32_t>(L.chunk_band.size());
   L.chunk_off.push_back(L.off[nb]);
+}
+
+// Spread chunks: consecutive entries of a band, at most the band's equal
+// share of ceil(n / max_entries) chunks each, cut earlier where the window
+// columns the stencils touch would span more than g.spread_cols (the
+// columns [c_lo, c_hi) of a chunk are rounded out to multiples of 4).  A
+// band's list runs in sample order, which moves steadily along the angle
+// inside one band, so a chunk spans a fraction of the window.  Records each
+// chunk's columns and the place of its partial rows (R x wc floats).
+void make_spread_chunks(const Geometry& g, int max_entries, BandLists& L) {
+  const int nb = g.nbands;
+  L.chunk_off.clear();
+  L.chunk_band.clear();
+  L.chunk_col.clear();
+  L.chunk_hp.clear();
+  L.band_chunk.assign(nb + 1, 0);
+  int64_t hp = 0;
+  auto close = [&](int b, int64_t start, int c_lo, int c_hi) {
+    L.chunk_off.push_back(start);
+    L.chunk_band.push_back(b);
+    const int wc = c_hi > c_lo ? c_hi - c_lo : 0;
+    L.chunk_col.push_back(wc ? c_lo : 0);
+    L.chunk_col.push_back(wc);
+    L.chunk_hp.push_back(hp);
+    hp += static_cast<int64_t>(g.R) * wc;
+  };
+  for (int b = 0; b < nb; ++b) {
+    L.band_chunk[b] = static_cast<int32_t>(L.chunk_band.size());
+    const int64_t lo = L.off[b], hi = L.off[b + 1], n = hi - lo;
+    const int64_t m = std::max<int64_t>(1, (n + max_entries - 1) / max_entries);
+    const int64_t share = std::max<int64_t>(1, (n + m - 1) / m);
+    int64_t start = lo;
+    int c_lo = 0, c_hi = 0;  // empty column range
+    for (int64_t i = lo; i < hi; ++i) {
+      const int cx = static_cast<int>(L.e[i].xq >> g.x_frac_bits) - 1;  // first tap column
+      const int a = cx & ~3, z = (cx + 4 + 3) & ~3;
+      const int n_lo = i == start ? a : std::min(c_lo, a);
+      const int n_hi = i == start ? z : std::max(c_hi, z);
+      if (i > start && (i - start == share || n_hi - n_lo > g.spread_cols)) {
+        close(b, start, c_lo, c_hi);
+        start = i;
+        c_lo = a;
+        c_hi = z;
+      } else {
+        c_lo = n_lo;
+        c_hi = n_hi;
+      }
+    }
+    close(b, start, c_lo, c_hi);
+  }
+  L.band_chunk[nb] = static_cast<int32_t>(L.chunk_band.size());
+  L.chunk_off.push_back(L.off[nb]);
+  L.hp_floats = hp;
 }
 
 // Band lists of one point set.  `place(p, xg, yg, w)` gives the coordinates
@@ -583,7 +641,7 @@ hrt_status build_lists(const Geometry& g, int64_t npts, PlaceF place, BandLists&
   auto ps = offsets(cs, spread);
   auto po = offsets(co, own);
   run(true, &ps, &po);
-  make_chunks(nb, kSpreadChunk, spread);
+  make_spread_chunks(g, kSpreadChunk, spread);
   make_chunks(nb, kGatherChunk, own);
   return HRT_OK;
 }

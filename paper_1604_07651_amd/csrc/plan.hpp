@@ -20,9 +20,10 @@ constexpr int kFftRadices[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
 // row items, or one item when it is lower).
 constexpr int kMaxBandRows = 8;
 constexpr int kRowRows = 4;
-// Bands taller than 4 rows are taken only while a spread workgroup's LDS
-// stays within this, so that several workgroups share a CU.
-constexpr int kBandLdsPreferred = 64 * 1024;
+// Dynamic LDS of a spread workgroup: its staging buffer and a 64-bit
+// accumulator of the band's rows over the chunk's columns, which bounds the
+// columns a spread chunk may span (three workgroups share a CU's 160 KB).
+constexpr int kSpreadLds = 50 * 1024;
 // Static LDS of the band kernels (twiddles, reduction slots), rounded up.
 constexpr int kBandStaticLds = 4096;
 // Threads of the band kernels and of the column kernel.
@@ -31,11 +32,12 @@ constexpr int kColThreads = 256;
 // The in-place FFT holds at most this many complex values per thread.
 constexpr int kInplaceValues = 16;
 // Point lists are cut into chunks of at most these many entries (spread:
-// each chunk writes one partial of its band's rows; gather: one workgroup),
-// and the spread stages kSpreadStage entries at a time in LDS.
+// each chunk writes one partial of its band's rows over the columns it
+// spans; gather: one workgroup), and the spread stages kSpreadStage entries
+// at a time in LDS.
 constexpr int kSpreadChunk = 5120;
 constexpr int kGatherChunk = 4096;
-constexpr int kSpreadStage = 1024;
+constexpr int kSpreadStage = 512;
 // Fraction bits of the log-radius coordinate in a point entry (the integer
 // part, the row relative to the band's first tap row, needs 3 bits).
 constexpr int kYFracBits = 28;
@@ -124,6 +126,7 @@ struct Geometry {
   int col_batch = 1;          // columns per workgroup of the column kernel
   int xw0 = 0, W = 0;         // angle columns [xw0, xw0 + W) points can touch (W % 4 == 0)
   int x_frac_bits = 0;         // fraction bits of the angle coordinate in a point entry
+  int spread_cols = 0;         // most window columns one spread chunk spans (% 4 == 0)
   // dynamic LDS per workgroup of the spread, row FFT, column and gather
   // kernels
   int spread_bytes = 0, row_bytes = 0, col_bytes = 0, gather_bytes = 0;
@@ -164,6 +167,14 @@ struct BandLists {
   std::vector<int64_t> chunk_off;
   std::vector<int32_t> chunk_band;
   std::vector<int32_t> band_chunk;
+  // spread lists only: the window columns [c_lo, c_lo + wc) that chunk c's
+  // stencils touch (c_lo and wc multiples of 4, wc <= spread_cols; wc = 0
+  // for an empty chunk) as chunk_col[2c], chunk_col[2c+1], and where its
+  // partial rows, R x wc floats, start in the partial buffer (hp_floats in
+  // all)
+  std::vector<int32_t> chunk_col;
+  std::vector<int64_t> chunk_hp;
+  int64_t hp_floats = 0;
 };
 
 struct PointTables {

@@ -6,24 +6,29 @@
 
 namespace hrt {
 
-// Adds v * B3(x - x_m) B3(y - y_n) over the taps of entry t to the band's
-// accumulator, in 32-bit fixed point: a tap value enters as round(tap *
-// scale) through the integer LDS atomic (float LDS atomics are far slower on
-// gfx950).  `v` arrives already multiplied by the scale, chosen so that
-// |every cell| <= 2^30 (the plan bounds the cells per unit input); integer
-// sums are exact and independent of order, so the band is deterministic.
-// Band row r, window column c is acc[r * W + c]; rows outside [0, nr) belong
-// to other bands and are dropped.
-__device__ __forceinline__ void spread_taps(int* acc, int W, int nr, const EntryTaps& t,
-                                            float v) {
+// Adds v * B3(x - x_m) B3(y - y_n) over the taps of entry t to the chunk's
+// accumulator in 64-bit fixed point: each tap is formed in float32 (so it
+// carries float32's relative precision whatever its size) and enters as
+// round(tap * scale) through the 64-bit integer LDS atomic.  `v` arrives
+// already multiplied by the scale, chosen so that |every cell| <= 2^61 (the
+// plan bounds the cells per unit input); the integer sums are exact and
+// independent of order, so a chunk's sums are deterministic and each cell is
+// rounded to float32 once, when the chunk stores it.  (Float LDS atomics
+// would give float32 sums, but they run about ten times slower than integer
+// ones on gfx950 and their order, hence their rounding, varies from run to
+// run.)  Band row r, window column c0 + c is acc[r * wc + c]; rows outside
+// [0, nr) belong to other bands and are dropped.
+__device__ __forceinline__ void spread_taps(unsigned long long* acc, int wc, int c0, int nr,
+                                            const EntryTaps& t, float v) {
 #pragma unroll
   for (int bb = 0; bb < 4; ++bb) {
     const int rl = t.cy + bb;
     if (rl < 0 || rl >= nr) continue;
-    int* row = acc + rl * W + t.cx;
+    unsigned long long* row = acc + rl * wc + (t.cx - c0);
     const float wr = v * t.wy[bb];
 #pragma unroll
-    for (int aa = 0; aa < 4; ++aa) atomicAdd(row + aa, __float2int_rn(wr * t.wx[aa]));
+    for (int aa = 0; aa < 4; ++aa)
+      atomicAdd(row + aa, static_cast<unsigned long long>(__float2ll_rn(wr * t.wx[aa])));
   }
 }
 

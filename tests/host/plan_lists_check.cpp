@@ -3,7 +3,10 @@
 // exactly one band, in index order, at a row inside that band; every
 // sample sits in the spread list of each band its 4 x 4 stencil reaches and
 // of no other; chunks tile the lists band by band within their size limits;
-// the Radon entries of one slowness share their angle coordinate and weight.
+// a spread chunk's column range holds every stencil of its entries, stays
+// within the accumulator's width and the window, and its partial rows follow
+// the previous chunk's; the Radon entries of one slowness share their angle
+// coordinate and weight.  Grids with band heights 8, 4 and 2 are covered.
 // Prints "ok" and exits 0, or prints the first failure and exits 1.
 #include <cmath>
 #include <cstdio>
@@ -46,12 +49,38 @@ static void check_chunks(const BandLists& L, int nb, int max_entries, const char
   }
 }
 
+static void check_spans(const Geometry& g, const BandLists& L, const char* what) {
+  const size_t nc = L.chunk_band.size();
+  CHECK(L.chunk_col.size() == 2 * nc && L.chunk_hp.size() == nc, "%s: span tables", what);
+  int64_t hp = 0;
+  for (size_t c = 0; c < nc; ++c) {
+    const int lo = L.chunk_col[2 * c], wc = L.chunk_col[2 * c + 1];
+    CHECK(lo % 4 == 0 && wc % 4 == 0 && lo >= 0 && wc >= 0, "%s: chunk %zu columns", what, c);
+    CHECK(wc <= g.spread_cols && lo + wc <= g.W, "%s: chunk %zu spans %d columns from %d",
+          what, c, wc, lo);
+    CHECK(L.chunk_hp[c] == hp, "%s: chunk %zu partial at %lld, want %lld", what, c,
+          static_cast<long long>(L.chunk_hp[c]), static_cast<long long>(hp));
+    hp += static_cast<int64_t>(g.R) * wc;
+    CHECK(L.chunk_off[c + 1] == L.chunk_off[c] || wc > 0, "%s: chunk %zu empty span", what, c);
+    for (int64_t i = L.chunk_off[c]; i < L.chunk_off[c + 1]; ++i) {
+      const int cx = static_cast<int>(L.e[i].xq >> g.x_frac_bits) - 1;
+      CHECK(cx >= lo && cx + 4 <= lo + wc, "%s: chunk %zu entry %lld taps %d..%d outside %d..%d",
+            what, c, static_cast<long long>(i), cx, cx + 3, lo, lo + wc - 1);
+    }
+  }
+  CHECK(L.hp_floats == hp, "%s: partial floats %lld, want %lld", what,
+        static_cast<long long>(L.hp_floats), static_cast<long long>(hp));
+  CHECK(static_cast<int64_t>(g.R) * g.spread_cols * 8 + int64_t{kSpreadStage} * 16 <= g.spread_bytes,
+        "%s: spread LDS", what);
+}
+
 // `expected`: the indices the point set must hold, in increasing order
 static void check_set(const Geometry& g, const BandLists& spread, const BandLists& own,
                       const std::vector<uint32_t>& expected, const char* what) {
   const int nb = g.nbands;
   check_chunks(spread, nb, kSpreadChunk, what);
   check_chunks(own, nb, kGatherChunk, what);
+  check_spans(g, spread, what);
   if (fails) return;
   // owned: each expected index once, band-major, increasing inside a band,
   // its row floor inside the band (a row within 2^-20 of an integer may
@@ -137,11 +166,16 @@ static void check_radon_slowness(const Geometry& g, const BandLists& spread,
     }
 }
 
-static void run(const char* name, const hrt_desc& d, const PartView* view) {
+static void run(const char* name, const hrt_desc& d, const PartView* view, int want_R = 0) {
   Geometry g;
   std::string err;
   if (build_geometry(d, 163840 - 4096, g, err, view) != HRT_OK) {
     std::printf("%s: geometry: %s\n", name, err.c_str());
+    ++fails;
+    return;
+  }
+  if (want_R && g.R != want_R) {
+    std::printf("%s: band height %d, want %d\n", name, g.R, want_R);
     ++fails;
     return;
   }
