@@ -74,11 +74,19 @@ typedef struct {
 
 /* Kernel variants, for tuning (results do not depend on them beyond float32
  * rounding): FFT radices at most 8 along the angle / the log radius (default
- * 16), two columns per workgroup in the column pass (default one). */
+ * 16); two columns per workgroup in the column pass (default one); row bands
+ * of the spread and gather kernels at most 4 or 2 lattice rows high (default
+ * 8, or lower where the LDS needs it; BAND2 wins over BAND4); spread chunks
+ * of at most 2560 point entries (default 5120); gather chunks of at most
+ * 8192 entries (default 4096). */
 #define HRT_TUNE_ROW_RADIX8 1
 #define HRT_TUNE_COL_RADIX8 2
 #define HRT_TUNE_COL_PAIRS 4
-#define HRT_TUNE_MASK 7
+#define HRT_TUNE_BAND4 8
+#define HRT_TUNE_BAND2 16
+#define HRT_TUNE_SPREAD_HALF 32
+#define HRT_TUNE_GATHER_DOUBLE 64
+#define HRT_TUNE_MASK 127
 
 /* What a plan computed (all host values). */
 typedef struct {

@@ -128,6 +128,10 @@ def check(status: int, where: str) -> None:
 TUNE_ROW_RADIX8 = 1
 TUNE_COL_RADIX8 = 2
 TUNE_COL_PAIRS = 4
+TUNE_BAND4 = 8
+TUNE_BAND2 = 16
+TUNE_SPREAD_HALF = 32
+TUNE_GATHER_DOUBLE = 64
 
 
 def make_desc(d, flags: int = 0) -> HrtDesc:

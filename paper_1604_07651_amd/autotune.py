@@ -1,8 +1,19 @@
-"""Autotuner of the kernel variants (FFT radices per axis, columns per
-workgroup of the column pass): times forward+adjoint of every variant on the
-device for a grid description and caches the fastest in a JSON file keyed by
-the grid and the device name.  Cache path: $HRT_TUNE_CACHE, else
-~/.cache/paper_1604_07651_amd/tune.json."""
+"""Autotuner of the kernel variants (HRT_TUNE_* bits of hrt_desc.flags):
+FFT radix caps per axis, columns per workgroup of the column pass, row-band
+height of the spread and gather kernels, spread and gather chunk sizes.
+
+The variants change only float32 rounding, not the operator.  The tuner
+times forward+adjoint of a grid on the device and walks the variant space one
+dimension at a time (coordinate search: every option of a dimension with the
+others held at the best so far, then the next dimension), which covers the
+48 combinations with about 15 timings.  The choice is cached in a JSON file
+keyed by the grid and the device name: $HRT_TUNE_CACHE, else
+~/.cache/paper_1604_07651_amd/tune.json; a cache shipped with the package
+(tune_cache.json, written by this module on an MI355X) is read when the user
+cache has no entry.
+
+    python -m paper_1604_07651_amd.autotune c3 [c2 ...] [--out FILE]
+tunes the named grid configurations and writes (merges) their entries."""
 from __future__ import annotations
 
 import json
@@ -12,7 +23,21 @@ import torch
 
 from . import _lib
 
-VARIANTS = [f for f in range(8)]  # every combination of the three HRT_TUNE_* bits
+# the dimensions of the search, each a list of mutually exclusive flag values
+DIMENSIONS = [
+    ("fft", [0, _lib.TUNE_ROW_RADIX8, _lib.TUNE_COL_RADIX8,
+             _lib.TUNE_ROW_RADIX8 | _lib.TUNE_COL_RADIX8, _lib.TUNE_COL_PAIRS,
+             _lib.TUNE_COL_PAIRS | _lib.TUNE_ROW_RADIX8,
+             _lib.TUNE_COL_PAIRS | _lib.TUNE_COL_RADIX8,
+             _lib.TUNE_COL_PAIRS | _lib.TUNE_ROW_RADIX8 | _lib.TUNE_COL_RADIX8]),
+    ("band_rows", [0, _lib.TUNE_BAND4, _lib.TUNE_BAND2]),
+    ("spread_chunk", [0, _lib.TUNE_SPREAD_HALF]),
+    ("gather_chunk", [0, _lib.TUNE_GATHER_DOUBLE]),
+]
+# every combination (for callers that time the whole space)
+VARIANTS = sorted({a | b | c | d for a in DIMENSIONS[0][1] for b in DIMENSIONS[1][1]
+                   for c in DIMENSIONS[2][1] for d in DIMENSIONS[3][1]})
+PACKAGED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
 def cache_path() -> str:
@@ -27,53 +52,115 @@ def key(desc, device=None) -> str:
     return f"{name}|{grid}|{float(getattr(desc, 'oversample', 2.0))!r}"
 
 
-def _load() -> dict:
+def _load(path) -> dict:
     try:
-        with open(cache_path()) as fh:
+        with open(path) as fh:
             return json.load(fh)
     except (OSError, ValueError):
         return {}
 
 
+def lookup(desc):
+    """The cached entry for `desc` on this device (user cache first, then
+    the packaged one), or None."""
+    k = key(desc)
+    for path in (cache_path(), PACKAGED):
+        entry = _load(path).get(k)
+        if entry:
+            return entry
+    return None
+
+
 def tuned_flags(desc) -> int:
     """Cached best variant for `desc` on this device (0 when not tuned)."""
-    entry = _load().get(key(desc))
+    entry = lookup(desc)
     return int(entry["flags"]) if entry else 0
 
 
-def tune(desc, reps: int = 10, variants=VARIANTS, save: bool = True) -> dict:
-    """Times forward+adjoint of each variant (random input, `reps` timed
-    pairs after two warm-up pairs, HIP events on the current stream) and
-    returns {"flags": best, "ms": {flags: ms per pair}}, cached if `save`."""
+def time_variant(desc, flags: int, reps: int = 10, rounds: int = 3) -> float:
+    """ms per forward+adjoint of one plan with `flags` (random input, two
+    warm-up pairs, then the best of `rounds` groups of `reps` timed pairs,
+    HIP events on the current stream)."""
     from .hrt import Plan
-    times = {}
     gen = torch.Generator(device="cuda").manual_seed(0)
-    for fl in variants:
-        plan = Plan(desc, flags=fl)
+    plan = Plan(desc, flags=flags)
+    try:
         f = torch.randn(plan.data_shape, device="cuda", generator=gen)
         g = torch.empty(plan.radon_shape, device="cuda")
         fa = torch.empty(plan.data_shape, device="cuda")
         for _ in range(2):
-            plan.forward(f, out=g)
-            plan.adjoint(g, out=fa)
-        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record()
-        for _ in range(reps):
-            plan.forward(f, out=g)
-            plan.adjoint(g, out=fa)
-        end.record()
-        end.synchronize()
-        times[fl] = start.elapsed_time(end) / reps
+            plan.normal(f, g=g, out=fa)
+        best = float("inf")
+        for _ in range(rounds):
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            start.record()
+            for _ in range(reps):
+                plan.normal(f, g=g, out=fa)
+            end.record()
+            end.synchronize()
+            best = min(best, start.elapsed_time(end) / reps)
+        return best
+    finally:
         plan.close()
-    best = min(times, key=times.get)
-    result = {"flags": int(best), "ms": {str(k): v for k, v in times.items()}}
+
+
+def tune(desc, reps: int = 10, variants=None, save: bool = True, path: str | None = None) -> dict:
+    """Finds the fastest variant for `desc`.  With `variants`, times exactly
+    those; otherwise searches DIMENSIONS one at a time.  Returns {"flags":
+    best, "ms": {flags: ms per forward+adjoint}}; saved to `path` (default
+    the user cache) when `save`."""
+    times = {}
+
+    def t(fl):
+        if fl not in times:
+            times[fl] = time_variant(desc, fl, reps)
+        return times[fl]
+
+    if variants is not None:
+        for fl in variants:
+            t(fl)
+        best = min(times, key=times.get)
+    else:
+        best = 0
+        for _, options in DIMENSIONS:
+            mask = 0
+            for o in options:
+                mask |= o
+            base = best & ~mask
+            best = min((base | o for o in options), key=t)
+    result = {"flags": int(best), "ms": {str(k): round(v, 5) for k, v in sorted(times.items())}}
     if save:
-        data = _load()
-        data[key(desc)] = result
-        path = cache_path()
-        os.makedirs(os.path.dirname(path), exist_ok=True)
-        tmp = path + ".tmp"
-        with open(tmp, "w") as fh:
-            json.dump(data, fh, indent=1)
-        os.replace(tmp, path)
+        save_entry(desc, result, path)
     return result
+
+
+def save_entry(desc, result: dict, path: str | None = None) -> None:
+    path = path or cache_path()
+    data = _load(path)
+    data[key(desc)] = result
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def main(argv=None) -> None:
+    import argparse
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import synth
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("configs", nargs="+", help="grid configurations (c1, c2, c3, ...)")
+    ap.add_argument("--out", default=None, help="cache file to write (default: user cache)")
+    ap.add_argument("--reps", type=int, default=10)
+    args = ap.parse_args(argv)
+    for name in args.configs:
+        desc = synth.config_desc(name)
+        res = tune(desc, reps=args.reps, path=args.out)
+        print(json.dumps({"config": name, **res}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

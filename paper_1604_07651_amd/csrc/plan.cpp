@@ -447,7 +447,9 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
   };
   // band heights 2, 4, 8, ...: a band holds a power-of-two number of row
   // pairs, and the last band an even number of rows not above it
-  g.R = kMaxBandRows;
+  g.R = (d.flags & HRT_TUNE_BAND2) ? 2 : (d.flags & HRT_TUNE_BAND4) ? 4 : kMaxBandRows;
+  g.spread_chunk = (d.flags & HRT_TUNE_SPREAD_HALF) ? kSpreadChunk / 2 : kSpreadChunk;
+  g.gather_chunk = (d.flags & HRT_TUNE_GATHER_DOUBLE) ? 2 * kGatherChunk : kGatherChunk;
   while (g.R > 2 && layout(g.R, false) > lds_bytes) g.R /= 2;
   if (layout(g.R, false) > lds_bytes || spread_cols(g.R) < 8)
     return fail(err, HRT_ERR_UNSUPPORTED, "angle axis too long for the LDS row bands");
@@ -641,8 +643,8 @@ hrt_status build_lists(const Geometry& g, int64_t npts, PlaceF place, BandLists&
   auto ps = offsets(cs, spread);
   auto po = offsets(co, own);
   run(true, &ps, &po);
-  make_spread_chunks(g, kSpreadChunk, spread);
-  make_chunks(nb, kGatherChunk, own);
+  make_spread_chunks(g, g.spread_chunk, spread);
+  make_chunks(nb, g.gather_chunk, own);
   return HRT_OK;
 }
 

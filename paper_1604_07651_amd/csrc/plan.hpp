@@ -31,10 +31,10 @@ constexpr int kBandThreads = 512;
 constexpr int kColThreads = 256;
 // The in-place FFT holds at most this many complex values per thread.
 constexpr int kInplaceValues = 16;
-// Point lists are cut into chunks of at most these many entries (spread:
-// each chunk writes one partial of its band's rows over the columns it
-// spans; gather: one workgroup), and the spread stages kSpreadStage entries
-// at a time in LDS.
+// Point lists are cut into chunks of at most these many entries by default
+// (spread: each chunk writes one partial of its band's rows over the
+// columns it spans; gather: one workgroup), and the spread stages
+// kSpreadStage entries at a time in LDS.
 constexpr int kSpreadChunk = 5120;
 constexpr int kGatherChunk = 4096;
 constexpr int kSpreadStage = 512;
@@ -127,6 +127,8 @@ struct Geometry {
   int xw0 = 0, W = 0;         // angle columns [xw0, xw0 + W) points can touch (W % 4 == 0)
   int x_frac_bits = 0;         // fraction bits of the angle coordinate in a point entry
   int spread_cols = 0;         // most window columns one spread chunk spans (% 4 == 0)
+  int spread_chunk = 0;        // most entries of a spread chunk
+  int gather_chunk = 0;        // most entries of a gather chunk
   // dynamic LDS per workgroup of the spread, row FFT, column and gather
   // kernels
   int spread_bytes = 0, row_bytes = 0, col_bytes = 0, gather_bytes = 0;

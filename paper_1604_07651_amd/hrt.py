@@ -267,13 +267,23 @@ class Batch:
     """Uneven batch of gathers transformed by one launch per kernel; arrays
     are packed 1-D float32 tensors (see offsets)."""
 
-    def __init__(self, descs, device=None):
+    def __init__(self, descs, device=None, flags=0, tuned: bool = False):
+        """flags: HRT_TUNE_* kernel variants, one int for every gather or
+        one per gather; tuned=True takes each gather's from the autotuner's
+        cache (its default where the cache has no entry)."""
         self._lib = _lib.load()
         self.descs = list(descs)
         n = len(self.descs)
         self.device = torch.device("cuda", torch.cuda.current_device()
                                    if device is None else torch.device(device).index)
-        arr = (_lib.HrtDesc * n)(*[_lib.make_desc(d) for d in self.descs])
+        if tuned:
+            from . import autotune
+            with torch.cuda.device(self.device):
+                flags = [autotune.tuned_flags(d) for d in self.descs]
+        self.flags = [int(flags)] * n if isinstance(flags, int) else [int(x) for x in flags]
+        if len(self.flags) != n:
+            raise ValueError("one flags value per gather")
+        arr = (_lib.HrtDesc * n)(*[_lib.make_desc(d, fl) for d, fl in zip(self.descs, self.flags)])
         handle = C.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(self._lib.hrt_batch_create(arr, n, C.byref(handle)), "hrt_batch_create")

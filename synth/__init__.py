@@ -6,11 +6,11 @@ both the FP64 oracle and the GPU library can be fed from it without sharing any
 code of the method.
 """
 from .gathers import (GridDesc, CONFIGS, config_desc, ricker, ricker_gather,
-                      config_gather, gaussian_sy_gather, trace_mask,
+                      config_gather, gaussian_sy_gather, band_limited_gather, trace_mask,
                       batch_descs, batch_gathers, random_pair, c5_batch,
                       demultiple_gather, s1_desc, s1_gather)
 
 __all__ = ["GridDesc", "CONFIGS", "config_desc", "ricker", "ricker_gather",
-           "config_gather", "gaussian_sy_gather", "trace_mask", "batch_descs",
+           "config_gather", "gaussian_sy_gather", "band_limited_gather", "trace_mask", "batch_descs",
            "batch_gathers", "random_pair", "c5_batch", "demultiple_gather",
            "s1_desc", "s1_gather"]

@@ -126,6 +126,27 @@ def config_gather(name: str, dtype=np.float64) -> np.ndarray:
                          c["tau"], noise=c["noise"], dtype=dtype)
 
 
+def band_limited_gather(desc: GridDesc, events: int, freq: float, seed: int,
+                        tau_range=("rel", 0.7, 0.85), vel=(1.5, 4.0), taper: float = 0.1,
+                        dtype=np.float64) -> np.ndarray:
+    """Hyperbolic Ricker events (as ricker_gather, no noise) that a single
+    log-polar part represents: late events (tau from 0.7 T), a low peak
+    frequency chosen by the caller, and a cosine taper to zero over the last
+    `taper` fraction of the time axis and of the offsets, so that the record
+    has no hard edge at t = T or x = X.  Shape (nx, nt)."""
+    f = ricker_gather(desc, events, freq, seed, tau_range, vel)
+    t = np.arange(desc.nt) * desc.dt
+    x = desc.x0 + np.arange(desc.nx) * desc.dx
+
+    def edge(u, top):
+        # 1 below (1 - taper) top, cosine to 0 at top
+        r = np.clip((u - (1.0 - taper) * top) / (taper * top), 0.0, 1.0)
+        return 0.5 * (1.0 + np.cos(np.pi * r))
+
+    f *= edge(x, desc.X)[:, None] * edge(t, desc.T)[None, :]
+    return f.astype(dtype)
+
+
 def gaussian_sy_gather(desc: GridDesc, cs: float, cy: float, width: float,
                        dtype=np.float64) -> np.ndarray:
     """f(t,x) = 2 xh exp(-((th^2-cs)^2 + (xh^2-cy)^2) / (2 width^2)),

@@ -78,8 +78,8 @@ static void check_spans(const Geometry& g, const BandLists& L, const char* what)
 static void check_set(const Geometry& g, const BandLists& spread, const BandLists& own,
                       const std::vector<uint32_t>& expected, const char* what) {
   const int nb = g.nbands;
-  check_chunks(spread, nb, kSpreadChunk, what);
-  check_chunks(own, nb, kGatherChunk, what);
+  check_chunks(spread, nb, g.spread_chunk, what);
+  check_chunks(own, nb, g.gather_chunk, what);
   check_spans(g, spread, what);
   if (fails) return;
   // owned: each expected index once, band-major, increasing inside a band,
@@ -214,9 +214,17 @@ int main() {
               (qmax - qmin) / 127, 2.0, 0};
   hrt_desc odd{37, 23, 0.01, 0.05, 0.03, 29, 19, 0.07, 0.01, 0.3, 0.021, 2.5, 0};
   hrt_desc ragged{301, 77, 0.004, 0.1, 0.025, 250, 61, 0.05, 0.0045, 0.22, 0.0075, 2.0, 0};
-  run("c1", c1, nullptr);
+  run("c1", c1, nullptr, 8);
   run("odd", odd, nullptr);
-  run("ragged", ragged, nullptr);
+  run("ragged", ragged, nullptr, 8);
+  // band heights 4 and 2, and the other chunk sizes
+  for (const hrt_desc* base : {&c1, &ragged}) {
+    hrt_desc d = *base;
+    d.flags = HRT_TUNE_BAND4 | HRT_TUNE_SPREAD_HALF;
+    run(base == &c1 ? "c1 band4" : "ragged band4", d, nullptr, 4);
+    d.flags = HRT_TUNE_BAND2 | HRT_TUNE_GATHER_DOUBLE;
+    run(base == &c1 ? "c1 band2" : "ragged band2", d, nullptr, 2);
+  }
   // the parts of two splits
   const int32_t te[] = {0, 96, 256}, qe[] = {0, 64, 128};
   const int32_t te2[] = {0, 120, 301}, qe2[] = {0, 20, 41, 61};

@@ -39,6 +39,16 @@ SMALL = {
     # (ping-pong passes)
     "long": synth.GridDesc(nt=6000, nx=96, dt=0.0007, x0=0.0, dx=1.5 / 95, ntau=6000,
                            nq=96, tau0=0.0, dtau=0.0007, q0=0.25, dq=(1 / 1.5 - 0.25) / 95),
+    # angle axis of 4320 points (the lattice width of the paper's N = 2^11
+    # row): the row FFTs take two row pairs through an LDS scratch
+    "ang4320": synth.GridDesc(nt=512, nx=2048, dt=0.008, x0=0.0, dx=4.0 / 2047, ntau=512,
+                              nq=192, tau0=0.0, dtau=0.008, q0=0.25,
+                              dq=(1 / 1.5 - 0.25) / 191),
+    # angle axis of 8640 points (the lattice width of the N = 2^12 row): the
+    # plan takes bands of 2 rows, one row pair per row-FFT workgroup
+    "ang8640": synth.GridDesc(nt=1024, nx=4096, dt=0.004, x0=0.0, dx=4.0 / 4095, ntau=1024,
+                              nq=192, tau0=0.0, dtau=0.004, q0=0.25,
+                              dq=(1 / 1.5 - 0.25) / 191),
 }
 
 _cache = {}
@@ -78,7 +88,7 @@ def test_kernel_multiplier_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", ["c1", "odd", "tiny", "ragged", "q0zero", "wide", "c2",
-                                  "long"])
+                                  "long", "ang4320", "ang8640"])
 @pytest.mark.parametrize("kind", ["random", "ricker"])
 def test_forward_and_adjoint_parity(name, kind):
     desc, plan, ora = setup(name)
@@ -257,6 +267,46 @@ def test_direct_sum_matches_oracle():
     assert abs(lhs - rhs) / abs(lhs) <= 1e-5
 
 
+def test_direct_sum_matches_oracle_c2():
+    """The GPU direct sum (the reference the metric compares against) at C2:
+    forward on a sample of 16 slowness rows, adjoint of a panel whose only
+    non-zero rows are a block of 16 slownesses (the oracle's adjoint of the
+    same block as a grid of its own)."""
+    desc, plan, ora = setup("c2")
+    f, g = synth.random_pair(desc, 12)
+    rows = np.arange(0, desc.nq, desc.nq // 16)
+    print("[gpu] direct c2", flush=True)
+    got = plan.direct_forward(to_gpu(f)).double().cpu().numpy()[rows]
+    ref = direct.forward(desc, f, rows=rows)
+    r = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"  direct forward rel-L2 {r:.2e}", flush=True)
+    assert r <= 1e-4
+    l0, n = 200, 16
+    gb = np.zeros_like(g)
+    gb[l0:l0 + n] = g[l0:l0 + n]
+    gota = plan.direct_adjoint(to_gpu(gb)).double().cpu().numpy()
+    sub = desc.with_(nq=n, q0=desc.q0 + l0 * desc.dq)
+    refa = direct.adjoint(sub, g[l0:l0 + n])
+    r = np.linalg.norm(gota - refa) / np.linalg.norm(refa)
+    print(f"  direct adjoint rel-L2 {r:.2e}", flush=True)
+    assert r <= 1e-4
+
+
+def test_log_polar_vs_direct_sum_band_limited_c3():
+    """Method accuracy at the benchmark's size: the GPU log-polar forward of
+    a band-limited C3 gather (late hyperbolic Ricker events of 30 Hz, edges
+    tapered) against the FP64 direct sum on 25 slowness rows, <= 1e-3."""
+    desc, plan, ora = setup("c3")
+    f = synth.band_limited_gather(desc, 20, 30.0, 7)
+    rows = np.arange(0, desc.nq, desc.nq // 24)
+    print("[gpu] band-limited c3 vs direct sum", flush=True)
+    lp = plan.forward(to_gpu(f)).double().cpu().numpy()[rows]
+    ds = direct.forward(desc, f, rows=rows)
+    r = np.linalg.norm(lp - ds) / np.linalg.norm(ds)
+    print(f"  LP(GPU) vs DS(FP64) rel-L2 {r:.2e}", flush=True)
+    assert r <= 1e-3
+
+
 def test_log_polar_agrees_with_direct_sum_on_band_limited_data():
     """Method accuracy on the GPU: a smooth Gaussian in (s, y) at C1."""
     desc, plan, ora = setup("c1")
@@ -286,30 +336,56 @@ def test_unaligned_input_matches_aligned():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("flags", range(1, 8))
-def test_kernel_variants_match_oracle(flags):
-    """Every HRT_TUNE_* variant (smaller FFT radices, column pairs) on the
-    ragged grid against the oracle, to the same bar as the default."""
+# every HRT_TUNE_* bit, alone and in combinations: smaller FFT radices,
+# column pairs, band heights 4 and 2, smaller spread chunks, larger gather
+# chunks
+VARIANT_FLAGS = list(range(1, 8)) + [8, 16, 32, 64, 8 | 32, 16 | 64, 16 | 4 | 32, 8 | 3 | 64]
+
+
+@pytest.mark.parametrize("flags", VARIANT_FLAGS)
+@pytest.mark.parametrize("name", ["ragged", "c2"])
+def test_kernel_variants_match_oracle(name, flags):
+    """Every kernel variant against the oracle, to the same bar as the
+    default; the plan's band height is the one the flags ask for."""
     from paper_1604_07651_amd.hrt import Plan
-    desc, _, ora = setup("ragged")
+    if name == "c2" and flags < 8:
+        pytest.skip("FFT-only variants are covered on the ragged grid")
+    desc, _, ora = setup(name)
     plan = Plan(desc, flags=flags)
+    want_rows = 2 if flags & 16 else 4 if flags & 8 else 8
+    assert plan.info["band_rows"] == want_rows
     f, g = synth.random_pair(desc, 90 + flags)
-    print(f"[gpu] variant {flags}", flush=True)
+    print(f"[gpu] variant {name} {flags}", flush=True)
     compare(plan.forward(to_gpu(f)).cpu().numpy(), ora.forward(f), f"forward flags {flags}")
     compare(plan.adjoint(to_gpu(g)).cpu().numpy(), ora.adjoint(g), f"adjoint flags {flags}")
     plan.close()
 
 
 def test_autotuner_caches_and_plans_use_it(tmp_path, monkeypatch):
+    """The coordinate search over the variant dimensions times every option
+    of each dimension, picks the fastest it timed, caches it; plans and
+    batches created with tuned=True take it."""
     from paper_1604_07651_amd import autotune
-    from paper_1604_07651_amd.hrt import Plan
+    from paper_1604_07651_amd.hrt import Batch, Plan
     monkeypatch.setenv("HRT_TUNE_CACHE", str(tmp_path / "tune.json"))
     desc = SMALL["c1"]
     print("[gpu] autotune c1", flush=True)
     res = autotune.tune(desc, reps=3)
-    assert set(res["ms"]) == {str(f) for f in autotune.VARIANTS}
-    assert res["flags"] == min(autotune.VARIANTS, key=lambda f: res["ms"][str(f)])
+    timed = {int(k) for k in res["ms"]}
+    for _, options in autotune.DIMENSIONS:
+        mask = 0
+        for o in options:
+            mask |= o
+        # every option of every dimension was timed with the others at some value
+        assert all(any((fl & mask) == o for fl in timed) for o in options)
+    assert res["flags"] == min(timed, key=lambda f: res["ms"][str(f)])
     assert autotune.tuned_flags(desc) == res["flags"]
     plan = Plan(desc, tuned=True)
     assert plan.flags == res["flags"]
     plan.close()
+    b = Batch([desc, SMALL["odd"]], tuned=True)
+    assert b.flags == [res["flags"], 0]
+    b.close()
+    # an explicit list of variants is timed exactly
+    res2 = autotune.tune(desc, reps=2, variants=[0, 8, 16], save=False)
+    assert set(res2["ms"]) == {"0", "8", "16"}

@@ -92,9 +92,12 @@ def test_describe_accepts_tuning_flags_and_rejects_others():
     lib = _lib.load()
     info = _lib.HrtInfo()
     d = synth.config_desc("c1")
-    for fl in range(8):
+    for fl in range(128):
         assert lib.hrt_plan_describe(C.byref(_lib.make_desc(d, fl)), C.byref(info)) == 0
-    assert lib.hrt_plan_describe(C.byref(_lib.make_desc(d, 8)), C.byref(info)) == 1
+        # the band height the flags ask for
+        want = 2 if fl & _lib.TUNE_BAND2 else 4 if fl & _lib.TUNE_BAND4 else 8
+        assert info.band_rows == want
+    assert lib.hrt_plan_describe(C.byref(_lib.make_desc(d, 128)), C.byref(info)) == 1
     assert lib.hrt_plan_describe(C.byref(_lib.make_desc(d, -1)), C.byref(info)) == 1
 
 
