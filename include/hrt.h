@@ -88,6 +88,22 @@ typedef struct {
 #define HRT_TUNE_GATHER_DOUBLE 64
 #define HRT_TUNE_MASK 127
 
+/* Behaviour flags (also in hrt_desc.flags):
+ * HRT_ACCUMULATE_OUTPUT  hrt_forward, hrt_adjoint, hrt_forward_noalloc and
+ *                        the split transforms add their result into the
+ *                        output array instead of overwriting it (samples the
+ *                        adjoint does not reach are left as they are).
+ *                        Refused by hrt_normal and by batches
+ *                        (HRT_ERR_INVALID_ARG); the composite entry points
+ *                        (ISTA, power iteration, demultiple) always
+ *                        overwrite their work arrays.
+ * HRT_DETERMINISTIC      accepted, changes nothing: every path already
+ *                        gives the same bits on every run (the spread sums
+ *                        exactly in integers, every float sum runs in a
+ *                        fixed order, no float atomics). */
+#define HRT_ACCUMULATE_OUTPUT 256
+#define HRT_DETERMINISTIC 512
+
 /* What a plan computed (all host values). */
 typedef struct {
   double T, X;                    /* rescaling lengths, eq. hypnorm         */

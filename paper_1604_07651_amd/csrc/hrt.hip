@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <set>
@@ -174,8 +175,21 @@ std::vector<int> row_items(const Geometry& g) {
   return out;
 }
 
+// Allocation-failure injection, for tests of the clean-up paths:
+// HRT_FAIL_ALLOC=k (k >= 1) in the environment makes the k-th device
+// allocation of every plan creation fail with HRT_ERR_OOM.
+thread_local long g_fail_countdown = 0;
+void arm_fail_alloc() {
+  const char* e = std::getenv("HRT_FAIL_ALLOC");
+  g_fail_countdown = e ? std::max(0L, std::atol(e)) : 0;
+}
+
 template <typename T>
 hrt_status dev_alloc(T** p, size_t count, size_t& total) {
+  if (g_fail_countdown > 0 && --g_fail_countdown == 0) {
+    *p = nullptr;
+    return set_err(HRT_ERR_OOM, "injected allocation failure (HRT_FAIL_ALLOC)");
+  }
   const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
   hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
   if (e != hipSuccess) return set_err(HRT_ERR_OOM, "hipMalloc failed");
@@ -369,6 +383,7 @@ hrt_status hrt_plan_describe(const hrt_desc* desc, hrt_info* out) {
 static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_plan_t* out) {
   if (!desc || !out) return set_err(HRT_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
+  arm_fail_alloc();
   int dev = 0;
   HRT_HIP(hipGetDevice(&dev), "hipGetDevice");
   hipDeviceProp_t prop;
@@ -779,10 +794,13 @@ static void run_chain(hrt_plan_t p, const float* in, float* out, hipStream_t st,
   }
 }
 
+// `user_call`: the public forward / adjoint, which honour the plan's
+// HRT_ACCUMULATE_OUTPUT (internal chains always overwrite).
 static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* stream,
-                               bool adjoint) {
+                               bool adjoint, bool user_call = false) {
   hrt_status s = check_plan(p);
   if (s != HRT_OK) return s;
+  const bool accumulate = user_call && (p->g.d.flags & HRT_ACCUMULATE_OUTPUT);
   if (!in || !out) return set_err(HRT_ERR_INVALID_ARG, "null array");
   const size_t n_data = static_cast<size_t>(p->g.d.nx) * p->g.d.nt;
   const size_t n_radon = static_cast<size_t>(p->g.d.nq) * p->g.d.ntau;
@@ -794,18 +812,21 @@ static hrt_status launch_chain(hrt_plan_t p, const float* in, float* out, void* 
     return set_err(HRT_ERR_INVALID_ARG, "input and output overlap");
   DeviceGuard guard(p->device);
   (void)hipGetLastError();  // do not report an earlier, unrelated error
-  run_chain(p, in, out, reinterpret_cast<hipStream_t>(stream), adjoint, false);
+  run_chain(p, in, out, reinterpret_cast<hipStream_t>(stream), adjoint, accumulate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, adjoint ? "adjoint launch" : "forward launch");
   return HRT_OK;
 }
 
+// (only for a plan that check_plan has accepted)
+static bool accumulates(hrt_plan_t p) { return p->g.d.flags & HRT_ACCUMULATE_OUTPUT; }
+
 hrt_status hrt_forward(hrt_plan_t p, const float* f, float* g, void* stream) {
-  return launch_chain(p, f, g, stream, false);
+  return launch_chain(p, f, g, stream, false, true);
 }
 
 hrt_status hrt_adjoint(hrt_plan_t p, const float* g, float* f, void* stream) {
-  return launch_chain(p, g, f, stream, true);
+  return launch_chain(p, g, f, stream, true, true);
 }
 
 hrt_status hrt_forward_noalloc(hrt_plan_t p, const float* f, float* g, void* stream) {
@@ -833,7 +854,7 @@ hrt_status hrt_forward_noalloc(hrt_plan_t p, const float* f, float* g, void* str
   G.Cr = reinterpret_cast<float*>(b + L.Cr);
   G.absmax = reinterpret_cast<float*>(b + L.absmax);
   (void)hipGetLastError();  // do not report an earlier, unrelated error
-  run_chain(p, f, g, reinterpret_cast<hipStream_t>(stream), false, false, false, &G);
+  run_chain(p, f, g, reinterpret_cast<hipStream_t>(stream), false, accumulates(p), false, &G);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, "forward launch");
   return HRT_OK;
@@ -968,6 +989,9 @@ hrt_status hrt_normal(hrt_plan_t p, const float* f, float* g, float* fa, void* s
   const size_t nr = static_cast<size_t>(p->g.d.nq) * p->g.d.ntau * sizeof(float);
   if (overlaps(f, nd, g, nr) || overlaps(g, nr, fa, nd))
     return set_err(HRT_ERR_INVALID_ARG, "input and output overlap");
+  if (accumulates(p))
+    return set_err(HRT_ERR_INVALID_ARG, "hrt_normal overwrites its outputs: not with "
+                                        "HRT_ACCUMULATE_OUTPUT");
   DeviceGuard guard(p->device);
   (void)hipGetLastError();  // do not report an earlier, unrelated error
   const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -1192,6 +1216,9 @@ hrt_status check_batch(hrt_batch_t b) {
 hrt_status hrt_batch_create(const hrt_desc* descs, int32_t n, hrt_batch_t* out) {
   if (!descs || !out || n < 1) return set_err(HRT_ERR_INVALID_ARG, "null argument or n < 1");
   *out = nullptr;
+  for (int i = 0; i < n; ++i)
+    if (descs[i].flags & HRT_ACCUMULATE_OUTPUT)
+      return set_err(HRT_ERR_INVALID_ARG, "batches do not take HRT_ACCUMULATE_OUTPUT");
   auto* b = new hrt_batch_s();
   b->magic = kBatchMagic;
   HRT_HIP(hipGetDevice(&b->device), "hipGetDevice");
@@ -1502,7 +1529,8 @@ hrt_status hrt_split_create(const hrt_desc* desc, int32_t n_t, const int32_t* t_
       b->data_off.assign(per + 1, 0);
       b->radon_off.assign(per + 1, 0);
       sp->phases[dir].push_back(b);
-      hrt_status s = build_batch_tables(b, std::vector<int>(per, k == 0 ? 0 : 1));
+      const bool acc = k > 0 || (desc->flags & HRT_ACCUMULATE_OUTPUT);
+      hrt_status s = build_batch_tables(b, std::vector<int>(per, acc ? 1 : 0));
       if (s != HRT_OK) {
         const std::string e = g_last_error;
         free_split(sp);
@@ -1538,7 +1566,8 @@ static hrt_status split_chain(hrt_split_t sp, const float* in, float* out, void*
   const auto& phases = sp->phases[adjoint ? 1 : 0];
   for (size_t k = 0; k < phases.size(); ++k) {
     hrt_batch_s* b = phases[k];
-    if (b->plans.size() == 1) run_chain(b->plans[0], in, out, st, adjoint, k > 0);
+    const bool acc = k > 0 || (sp->d.flags & HRT_ACCUMULATE_OUTPUT);
+    if (b->plans.size() == 1) run_chain(b->plans[0], in, out, st, adjoint, acc);
     else run_batch(b, in, out, st, adjoint);
   }
   hipError_t e = hipGetLastError();

@@ -189,7 +189,7 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
     return fail(err, HRT_ERR_INVALID_ARG, "tau range exceeds the time range");
   if (!(d.oversample >= 1.5))
     return fail(err, HRT_ERR_INVALID_ARG, "oversampling must be >= 1.5");
-  if (d.flags & ~HRT_TUNE_MASK)
+  if (d.flags & ~(HRT_TUNE_MASK | HRT_ACCUMULATE_OUTPUT | HRT_DETERMINISTIC))
     return fail(err, HRT_ERR_INVALID_ARG, "unknown flags");
   if (static_cast<int64_t>(d.nt) * d.nx > (int64_t(1) << 31) ||
       static_cast<int64_t>(d.ntau) * d.nq > (int64_t(1) << 31))
