@@ -108,20 +108,19 @@ __global__ __launch_bounds__(256) void k_absmax(DevGeo one, const DevGeo* __rest
     G.absmax[w.i] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
 }
 
-// The spread's fixed-point scale: every accumulated cell stays within 2^61
-// (cmax bounds a cell per unit of input); 0 for an all-zero or non-finite
-// input (the latter is reported through `finite`).
-__device__ __forceinline__ float spread_scale(const DevGeo& G, float cmax, float* s_wave,
-                                              bool& finite) {
+// The spread's fixed-point scale (float64): every accumulated cell and
+// every tap stays within 2^50 (cmax bounds a cell per unit of input, and a
+// single tap by as much); 0 for an all-zero or non-finite input (the latter
+// is reported through `finite`).
+__device__ __forceinline__ double spread_scale(const DevGeo& G, float cmax, float* s_wave,
+                                               bool& finite) {
   float vmax = 0.0f;
   for (int i = threadIdx.x; i < G.absmax_blocks; i += kNtBand) vmax = fmaxf(vmax, G.absmax[i]);
   vmax = block_max(vmax, s_wave);
   finite = vmax <= 3.0e38f;  // false for inf and NaN
-  // 2^61 / (cmax vmax), formed in float64 so that neither factor can
-  // overflow float32 on the way
   return (vmax > 0.0f && finite)
-             ? static_cast<float>(2305843009213693952.0 / (static_cast<double>(cmax) * vmax))
-             : 0.0f;
+             ? 1125899906842624.0 / (static_cast<double>(cmax) * vmax)  // 2^50 / (cmax vmax)
+             : 0.0;
 }
 
 // Spread of one chunk (MODE 0: data samples of f[nx][nt]; MODE 1: Radon
@@ -153,10 +152,10 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
   unsigned long long* acc = lds_q;
   uint4* stage = reinterpret_cast<uint4*>(lds_q + G.R * G.spread_cols);
   bool finite;
-  const float scale = spread_scale(G, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave, finite);
+  const double scale = spread_scale(G, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave, finite);
   for (int i = threadIdx.x; i < nr * wc; i += kNtBand) acc[i] = 0ull;
   __syncthreads();
-  if (scale > 0.0f) {
+  if (scale > 0.0) {
     const int64_t e0 = L.chunk_off[chunk], e1 = L.chunk_off[chunk + 1];
     // data points: lane l of wave v takes segment (l % 8) * (kNtBand / 8) +
     // 8 v + l / 8, the eight lane groups of a wave an eighth of the stage
@@ -192,7 +191,8 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
         for (int t = 0; t < 4; ++t) {
           if (v[t] != 0.0f) {
             const EntryTaps tp = decode_entry(E[t].y, E[t].z, G.x_frac_bits);
-            spread_taps(acc, wc, cols.x, nr, tp, v[t] * __uint_as_float(E[t].w) * scale);
+            spread_taps(acc, wc, cols.x, nr, tp,
+                        static_cast<double>(v[t]) * __uint_as_float(E[t].w) * scale);
           }
         }
       }
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
   }
   // the chunk's partial rows, R x wc (rows past nr unused), each exact sum
   // rounded to float32
-  const double inv = scale > 0.0f ? 1.0 / static_cast<double>(scale) : 0.0;
+  const double inv = scale > 0.0 ? 1.0 / scale : 0.0;
   float* dst = G.Hp + L.chunk_hp[chunk];
   for (int i = threadIdx.x; i < nr * wc; i += kNtBand)
     dst[i] = static_cast<float>(static_cast<double>(static_cast<long long>(acc[i])) * inv);
