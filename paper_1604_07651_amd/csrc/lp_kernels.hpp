@@ -126,12 +126,11 @@ __device__ __forceinline__ double spread_scale(const DevGeo& G, float cmax, floa
 // Spread of one chunk (MODE 0: data samples of f[nx][nt]; MODE 1: Radon
 // samples of g[nq][ntau]); item i is chunk i of the spread list.  Dynamic
 // LDS: the band's R rows over the chunk's wc columns [c_lo, c_lo + wc) as
-// 64-bit fixed-point cells (R x spread_cols reserved), then a staging
-// buffer for kSpreadStage entries.  The chunk's entries are read coalesced
-// into the staging buffer; thread s then takes a contiguous segment of it,
-// segments dealt so that the lanes of a wave work far apart on the lattice.
-// The chunk's exact sums are rounded once to float32 into its partial rows,
-// R x wc floats at Hp + chunk_hp[chunk].
+// 64-bit fixed-point cells (R x spread_cols reserved).  Each thread reads
+// its entries straight from the list, kNtBand entries apart, dealt so that
+// the lanes of a wave work far apart on the lattice.  The chunk's exact
+// sums are rounded once to float32 into its partial rows, R x wc floats at
+// Hp + chunk_hp[chunk].
 template <int MODE, bool BATCH>
 __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __restrict__ geos,
                                                     const int2* __restrict__ items,
@@ -150,55 +149,44 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
   const int2 cols = L.chunk_col[chunk];  // {c_lo, wc}
   const int wc = cols.y;
   unsigned long long* acc = lds_q;
-  uint4* stage = reinterpret_cast<uint4*>(lds_q + G.R * G.spread_cols);
   bool finite;
   const double scale = spread_scale(G, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave, finite);
   for (int i = threadIdx.x; i < nr * wc; i += kNtBand) acc[i] = 0ull;
   __syncthreads();
   if (scale > 0.0) {
     const int64_t e0 = L.chunk_off[chunk], e1 = L.chunk_off[chunk + 1];
-    // data points: lane l of wave v takes segment (l % 8) * (kNtBand / 8) +
-    // 8 v + l / 8, the eight lane groups of a wave an eighth of the stage
-    // apart; Radon points (runs of one slowness share their columns):
-    // segment 101 t mod kNtBand, lanes scattered over the stage (both
-    // measured fastest for their point set)
+    // the chunk is taken kNtBand entries at a time, thread t doing entry
+    // seg(t) of each block: data points: lane l of wave v takes (l % 8) *
+    // (kNtBand / 8) + 8 v + l / 8, the eight lane groups of a wave an eighth
+    // of the block apart; Radon points (runs of one slowness share their
+    // columns): 101 t mod kNtBand, lanes scattered over the block (both
+    // measured fastest for their point set).  Entries are read straight
+    // from the list (a block is 4-8 KB, cached); each thread's entry two
+    // blocks ahead and its value one block ahead are in flight while it
+    // adds the current point's taps.
     const int seg = MODE == 0 ? (threadIdx.x & 7) * (kNtBand / 8) + (threadIdx.x >> 3)
                               : (threadIdx.x * 101) & (kNtBand - 1);
     static_assert((kNtBand & (kNtBand - 1)) == 0, "segment permutation needs a power of two");
-    for (int64_t c0 = e0; c0 < e1; c0 += kSpreadStage) {
-      const int n = static_cast<int>(min(static_cast<int64_t>(kSpreadStage), e1 - c0));
-      if (MODE == 1) {  // compact Radon entries
-        uint2* stage2 = reinterpret_cast<uint2*>(stage);
-        for (int i = threadIdx.x; i < n; i += kNtBand) stage2[i] = L.ent2[c0 + i];
-      } else {
-        for (int i = threadIdx.x; i < n; i += kNtBand) stage[i] = L.ent[c0 + i];
+    auto entry = [&](int64_t e) {
+      if (e >= e1) return make_uint4(0u, 0u, 0u, 0u);
+      return MODE == 1 ? radon_entry(G, L.ent2[e]) : L.ent[e];
+    };
+    int64_t c0 = e0 + seg;
+    uint4 E0 = entry(c0), E1 = entry(c0 + kNtBand);
+    float v0 = c0 < e1 ? in[E0.x] : 0.0f;
+    for (; c0 < e1; c0 += kNtBand) {
+      const float v1 = c0 + kNtBand < e1 ? in[E1.x] : 0.0f;
+      const uint4 E2 = entry(c0 + 2 * kNtBand);
+      if (v0 != 0.0f) {
+        const EntryTaps tp = decode_entry(E0.y, E0.z, G.x_frac_bits);
+        spread_taps(acc, wc, cols.x, nr, tp, static_cast<double>(v0) * __uint_as_float(E0.w) * scale);
       }
-      __syncthreads();
-      const int per = (n + kNtBand - 1) / kNtBand;
-      int p = seg * per;
-      const int pend = min(p + per, n);
-      for (; p < pend; p += 4) {
-        uint4 E[4];
-        float v[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          E[t] = (p + t >= pend) ? make_uint4(0, 0, 0, 0)
-                 : MODE == 1     ? radon_entry(G, reinterpret_cast<const uint2*>(stage)[p + t])
-                                 : stage[p + t];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) v[t] = (p + t < pend) ? in[E[t].x] : 0.0f;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          if (v[t] != 0.0f) {
-            const EntryTaps tp = decode_entry(E[t].y, E[t].z, G.x_frac_bits);
-            spread_taps(acc, wc, cols.x, nr, tp,
-                        static_cast<double>(v[t]) * __uint_as_float(E[t].w) * scale);
-          }
-        }
-      }
-      __syncthreads();
+      E0 = E1;
+      E1 = E2;
+      v0 = v1;
     }
   }
+  __syncthreads();
   // the chunk's partial rows, R x wc (rows past nr unused), each exact sum
   // rounded to float32
   const double inv = scale > 0.0 ? 1.0 / scale : 0.0;

@@ -418,15 +418,14 @@ hrt_status build_geometry(const hrt_desc& d, int64_t lds_bytes, Geometry& g,
       if (fft_fits_inplace(g.fft_t, b, kBandThreads, kInplaceValues)) grp = b;
     return grp;
   };
-  // columns a spread chunk may span: its 64-bit accumulator of R rows and
-  // the staging buffer fill kSpreadLds (at most the whole window)
+  // columns a spread chunk may span: its 64-bit accumulator of R rows fills
+  // kSpreadLds (at most the whole window)
   auto spread_cols = [&](int R) {
-    const int64_t c = (int64_t{kSpreadLds} - int64_t{kSpreadStage} * 16) / (int64_t{R} * 8);
+    const int64_t c = int64_t{kSpreadLds} / (int64_t{R} * 8);
     return static_cast<int>(std::min<int64_t>(g.W, c & ~int64_t{3}));
   };
   auto layout = [&](int R, bool commit) {
-    const int64_t spread =
-        static_cast<int64_t>(R) * spread_cols(R) * 8 + int64_t{kSpreadStage} * 16;
+    const int64_t spread = static_cast<int64_t>(R) * spread_cols(R) * 8;
     const int rr = std::min(R, kRowRows);  // rows of a row-FFT item
     const int grp = inplace_group(rr / 2);
     const int64_t pairs = (rr / 2) * seq;

@@ -20,9 +20,9 @@ constexpr int kFftRadices[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
 // row items, or one item when it is lower).
 constexpr int kMaxBandRows = 8;
 constexpr int kRowRows = 4;
-// Dynamic LDS of a spread workgroup: its staging buffer and a 64-bit
-// accumulator of the band's rows over the chunk's columns, which bounds the
-// columns a spread chunk may span (three workgroups share a CU's 160 KB).
+// Dynamic LDS of a spread workgroup: the 64-bit accumulator of the band's
+// rows over the chunk's columns, which bounds the columns a spread chunk may
+// span (800 at 8 rows; 38 and 30 KB measured slower at C3).
 constexpr int kSpreadLds = 50 * 1024;
 // Static LDS of the band kernels (twiddles, reduction slots), rounded up.
 constexpr int kBandStaticLds = 4096;
@@ -33,11 +33,9 @@ constexpr int kColThreads = 256;
 constexpr int kInplaceValues = 16;
 // Point lists are cut into chunks of at most these many entries by default
 // (spread: each chunk writes one partial of its band's rows over the
-// columns it spans; gather: one workgroup), and the spread stages
-// kSpreadStage entries at a time in LDS.
+// columns it spans; gather: one workgroup).
 constexpr int kSpreadChunk = 5120;
 constexpr int kGatherChunk = 4096;
-constexpr int kSpreadStage = 512;
 // Fraction bits of the log-radius coordinate in a point entry (the integer
 // part, the row relative to the band's first tap row, needs 3 bits).
 constexpr int kYFracBits = 28;

@@ -70,7 +70,7 @@ static void check_spans(const Geometry& g, const BandLists& L, const char* what)
   }
   CHECK(L.hp_floats == hp, "%s: partial floats %lld, want %lld", what,
         static_cast<long long>(L.hp_floats), static_cast<long long>(hp));
-  CHECK(static_cast<int64_t>(g.R) * g.spread_cols * 8 + int64_t{kSpreadStage} * 16 <= g.spread_bytes,
+  CHECK(static_cast<int64_t>(g.R) * g.spread_cols * 8 <= g.spread_bytes,
         "%s: spread LDS", what);
 }
 
