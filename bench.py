@@ -293,6 +293,7 @@ def batch_c4(torch, np, n=64, reps=10):
     import ctypes as C
     import synth
     from paper_1604_07651_amd.hrt import Batch
+    from paper_1604_07651_amd import autotune
     descs = synth.batch_descs(n, seed=4)
     fs = synth.batch_gathers(descs)
     b = Batch(descs)
@@ -331,6 +332,26 @@ def batch_c4(torch, np, n=64, reps=10):
         out[name] = {"ms_per_batch": round(sec * 1e3, 3), "gathers_per_s": round(n / sec, 1)}
     out["speedup"] = round(out["per_gather"]["ms_per_batch"] / out["batched"]["ms_per_batch"], 2)
     b.close()
+    # the same batch with the kernel variants the autotuner picked for this
+    # batch as a whole (its cache, or the one shipped with the package)
+    flags = autotune.batch_flags(descs)
+    bt = Batch(descs, flags=flags)
+    Ft = bt.pack_data(fs)
+    gt = bt.forward(Ft)
+    fat = bt.adjoint(gt)
+    for _ in range(2):
+        bt.forward(Ft, out=gt)
+        bt.adjoint(gt, out=fat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bt.forward(Ft, out=gt)
+        bt.adjoint(gt, out=fat)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    out["batched_tuned"] = {"ms_per_batch": round(sec * 1e3, 3), "gathers_per_s": round(n / sec, 1),
+                            "flags": flags}
+    bt.close()
     return out
 
 

@@ -12,8 +12,10 @@ keyed by the grid and the device name: $HRT_TUNE_CACHE, else
 (tune_cache.json, written by this module on an MI355X) is read when the user
 cache has no entry.
 
-    python -m paper_1604_07651_amd.autotune c3 [c2 ...] [--out FILE]
-tunes the named grid configurations and writes (merges) their entries."""
+    python -m paper_1604_07651_amd.autotune c3 [c2 c4 c4batch ...] [--out FILE]
+tunes the named grid configurations (c4: every distinct gather shape of the
+64-gather uneven batch; c4batch: that batch as a whole) and writes (merges)
+their entries."""
 from __future__ import annotations
 
 import json
@@ -135,15 +137,90 @@ def tune(desc, reps: int = 10, variants=None, save: bool = True, path: str | Non
     return result
 
 
-def save_entry(desc, result: dict, path: str | None = None) -> None:
-    path = path or cache_path()
-    data = _load(path)
-    data[key(desc)] = result
+def batch_key(descs, device=None) -> str:
+    """Cache key of an uneven batch: its gathers' grid keys, in order."""
+    import hashlib
+    h = hashlib.sha256("\n".join(key(d, device) for d in descs).encode()).hexdigest()[:20]
+    return f"batch|{torch.cuda.get_device_name(device)}|{len(descs)}|{h}"
+
+
+def time_batch(descs, flags: int, reps: int = 5, rounds: int = 3) -> float:
+    """ms per forward+adjoint of the whole batch, every gather with `flags`."""
+    from .hrt import Batch
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    b = Batch(descs, flags=flags)
+    try:
+        f = torch.randn(b.data_off[-1], device="cuda", generator=gen)
+        g = b.forward(f)
+        fa = b.adjoint(g)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(rounds):
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            start.record()
+            for _ in range(reps):
+                b.forward(f, out=g)
+                b.adjoint(g, out=fa)
+            end.record()
+            end.synchronize()
+            best = min(best, start.elapsed_time(end) / reps)
+        return best
+    finally:
+        b.close()
+
+
+def tune_batch(descs, reps: int = 5, save: bool = True, path: str | None = None) -> dict:
+    """The variant for a whole uneven batch (one flags value for all its
+    gathers), by the same coordinate search over the batch's own timing:
+    the best variant of a gather alone need not be the best inside a batch,
+    where the work items of all gathers share each launch."""
+    times = {}
+
+    def t(fl):
+        if fl not in times:
+            times[fl] = time_batch(descs, fl, reps)
+        return times[fl]
+
+    best = 0
+    for _, options in DIMENSIONS:
+        mask = 0
+        for o in options:
+            mask |= o
+        base = best & ~mask
+        best = min((base | o for o in options), key=t)
+    result = {"flags": int(best), "ms": {str(k): round(v, 5) for k, v in sorted(times.items())}}
+    if save:
+        path = path or cache_path()
+        data = _load(path)
+        data[batch_key(descs)] = result
+        _store(path, data)
+    return result
+
+
+def batch_flags(descs) -> int:
+    """Cached variant of the batch `descs` on this device (0 if not tuned)."""
+    k = batch_key(descs)
+    for path in (cache_path(), PACKAGED):
+        entry = _load(path).get(k)
+        if entry:
+            return int(entry["flags"])
+    return 0
+
+
+def _store(path: str, data: dict) -> None:
     os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
     tmp = path + ".tmp"
     with open(tmp, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
     os.replace(tmp, path)
+
+
+def save_entry(desc, result: dict, path: str | None = None) -> None:
+    path = path or cache_path()
+    data = _load(path)
+    data[key(desc)] = result
+    _store(path, data)
 
 
 def main(argv=None) -> None:
@@ -157,9 +234,20 @@ def main(argv=None) -> None:
     ap.add_argument("--reps", type=int, default=10)
     args = ap.parse_args(argv)
     for name in args.configs:
-        desc = synth.config_desc(name)
-        res = tune(desc, reps=args.reps, path=args.out)
-        print(json.dumps({"config": name, **res}), flush=True)
+        if name == "c4batch":
+            res = tune_batch(synth.batch_descs(64, seed=4), path=args.out)
+            print(json.dumps({"config": name, **res}), flush=True)
+            continue
+        if name == "c4":
+            seen = {}
+            for d in synth.batch_descs(64, seed=4):
+                seen.setdefault((d.nt, d.nx), d)
+            descs = [(f"c4 {nt}x{nx}", d) for (nt, nx), d in sorted(seen.items())]
+        else:
+            descs = [(name, synth.config_desc(name))]
+        for label, desc in descs:
+            res = tune(desc, reps=args.reps, path=args.out)
+            print(json.dumps({"config": label, **res}), flush=True)
 
 
 if __name__ == "__main__":

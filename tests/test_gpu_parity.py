@@ -389,3 +389,9 @@ def test_autotuner_caches_and_plans_use_it(tmp_path, monkeypatch):
     # an explicit list of variants is timed exactly
     res2 = autotune.tune(desc, reps=2, variants=[0, 8, 16], save=False)
     assert set(res2["ms"]) == {"0", "8", "16"}
+    # a batch is tuned as a whole, one variant for all its gathers
+    descs = [desc, SMALL["odd"], SMALL["ragged"]]
+    res3 = autotune.tune_batch(descs, reps=2)
+    assert res3["flags"] == min((int(k) for k in res3["ms"]), key=lambda f: res3["ms"][str(f)])
+    assert autotune.batch_flags(descs) == res3["flags"]
+    assert autotune.batch_flags(descs[:2]) == 0  # another batch: not tuned
