@@ -49,6 +49,16 @@ SMALL = {
     "ang8640": synth.GridDesc(nt=1024, nx=4096, dt=0.004, x0=0.0, dx=4.0 / 4095, ntau=1024,
                               nq=192, tau0=0.0, dtau=0.004, q0=0.25,
                               dq=(1 / 1.5 - 0.25) / 191),
+    # the smallest grid the boundary takes (4 samples on every axis), and
+    # grids of 4 time samples or 4 traces
+    "min4": synth.GridDesc(nt=4, nx=4, dt=0.01, x0=0.0, dx=0.02, ntau=4, nq=4, tau0=0.0,
+                           dtau=0.01, q0=0.25, dq=0.1),
+    "nt4": synth.GridDesc(nt=4, nx=200, dt=0.1, x0=0.0, dx=0.01, ntau=4, nq=4, tau0=0.0,
+                          dtau=0.1, q0=0.25, dq=0.1),
+    "nx4": synth.GridDesc(nt=300, nx=4, dt=0.004, x0=0.0, dx=0.5, ntau=300, nq=4, tau0=0.0,
+                          dtau=0.004, q0=0.25, dq=0.1),
+    # the paper's N = 2^12 grid of the size sweep, whole (dot test only)
+    "s4096": synth.s1_desc(4096),
 }
 
 _cache = {}
@@ -88,7 +98,7 @@ def test_kernel_multiplier_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", ["c1", "odd", "tiny", "ragged", "q0zero", "wide", "c2",
-                                  "long", "ang4320", "ang8640"])
+                                  "long", "ang4320", "ang8640", "min4", "nt4", "nx4"])
 @pytest.mark.parametrize("kind", ["random", "ricker"])
 def test_forward_and_adjoint_parity(name, kind):
     desc, plan, ora = setup(name)
@@ -114,9 +124,24 @@ def test_forward_and_adjoint_parity(name, kind):
     assert np.all(got[~ora.geo.keep] == 0.0)
 
 
-@pytest.mark.parametrize("name", ["c1", "ragged", "c2"])
+def setup_plan_only(name):
+    """A plan without the oracle (grids too large for it)."""
+    key = ("plan", name)
+    if key not in _cache:
+        from paper_1604_07651_amd.hrt import Plan
+        desc = SMALL[name] if name in SMALL else synth.config_desc(name)
+        print(f"[plan] {name}", flush=True)
+        _cache[key] = (desc, Plan(desc), None)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("name", ["c1", "ragged", "c2", "min4", "c3", "s4096"])
 def test_dot_product_float32(name):
-    desc, plan, ora = setup(name)
+    """The adjoint identity <R f, g> = <f, R* g> in float32 (a property that
+    holds at any size, so it also checks the full C3 grid and the N = 2^12
+    grid of the size sweep, 8640 x 6250 lattice with 2-row bands, which the
+    oracle cannot transform in seconds)."""
+    desc, plan, ora = (setup(name) if name not in ("c3", "s4096") else setup_plan_only(name))
     f, g = synth.random_pair(desc, 33)
     F, G = to_gpu(f), to_gpu(g)
     print(f"[gpu] dot {name}", flush=True)

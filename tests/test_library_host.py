@@ -139,3 +139,16 @@ def test_host_split_rejects_bad_edges():
                 hrt.describe_part(d, te, qe, i)
     with pytest.raises(_lib.HrtError):
         hrt.describe_part(d, [0, 128, 256], [0, 128], 2)
+
+
+def test_sector_wider_than_the_method_allows_is_refused():
+    """Slownesses from 0 to 0.6 s/km over offsets to 1.5 km at 0.4 s span
+    a sector whose kernel half-width reaches 1.5 rad (cos -> 0 in the
+    kernel's 1/cos): the plan refuses it as a geometry error before any
+    allocation."""
+    lib = _lib.load()
+    info = _lib.HrtInfo()
+    d = synth.GridDesc(nt=5, nx=4, dt=0.1, x0=0.0, dx=0.5, ntau=4, nq=5, tau0=0.0,
+                       dtau=0.1, q0=0.0, dq=0.15)
+    assert lib.hrt_plan_describe(C.byref(_lib.make_desc(d)), C.byref(info)) == 2
+    assert b"sector" in lib.hrt_last_error()
