@@ -188,11 +188,13 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
   }
   __syncthreads();
   // the chunk's partial rows, R x wc (rows past nr unused), each exact sum
-  // rounded to float32
+  // rounded to float32; NaN throughout for a non-finite input, which the
+  // row FFTs carry into every row (and the column pass into every column)
   const double inv = scale > 0.0 ? 1.0 / scale : 0.0;
   float* dst = G.Hp + L.chunk_hp[chunk];
   for (int i = threadIdx.x; i < nr * wc; i += kNtBand)
-    dst[i] = static_cast<float>(static_cast<double>(static_cast<long long>(acc[i])) * inv);
+    dst[i] = finite ? static_cast<float>(static_cast<double>(static_cast<long long>(acc[i])) * inv)
+                    : __int_as_float(0x7fc00000);
 }
 
 static_assert(kMaxBandRows >= 2 && (kMaxBandRows & (kMaxBandRows - 1)) == 0,
@@ -207,8 +209,7 @@ __device__ __forceinline__ int pair_shift(int npair) {
 
 // Row FFT of row_rows rows of a band (item i: band i >> row_sub_shift, the
 // rows from (i mod 2^row_sub_shift) * row_rows on): the sum of the band's
-// chunks' float32 partials of those rows, in chunk order (NaN everywhere
-// for a non-finite input), rows
+// chunks' float32 partials of those rows, in chunk order, rows
 // (2p, 2p+1) into complex pair p, FFT along the angle, and the k1 < K1 half
 // spectrum of both rows to S.  Dynamic LDS: the pairs, then the FFT scratch
 // (if any).
@@ -217,7 +218,6 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
                                                        const DevGeo* __restrict__ geos,
                                                        const int2* __restrict__ items) {
   extern __shared__ float2 lds[];
-  __shared__ float s_wave[kNtBand / 64];
   __shared__ float2 s_tw[kTwLds];
   const Work w = work_item<BATCH>(one, geos, items);
   if (w.i < 0) return;  // a gap in the XCD-ordered items
@@ -230,22 +230,19 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
   const int nr = min(G.row_rows, G.u1 - n0);
   const int npair = nr >> 1;
   const int Mt = G.Mt, W = G.W, SP = padded_len(G.Mt);
-  bool finite;
-  (void)spread_scale(G, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave, finite);
-  const float bad = finite ? 0.0f : __int_as_float(0x7fc00000);
   const int q0 = L.band_chunk[band], q1 = L.band_chunk[band + 1];
   // angle columns outside the window hold no point: zero
   for (int p = 0; p < npair; ++p)
     for (int m = threadIdx.x; m < Mt; m += kNtBand)
-      if (m < G.xw0 || m >= G.xw0 + W) lds[p * SP + lpad(m)] = make_float2(0.0f + bad, 0.0f + bad);
+      if (m < G.xw0 || m >= G.xw0 + W) lds[p * SP + lpad(m)] = make_float2(0.0f, 0.0f);
   // the window: the sum over the band's chunks, in chunk order, of their
   // float32 partials; chunk q holds rows x columns [c_lo, c_lo + wc) of the
   // band (c_lo, wc multiples of 4, so a 16-byte group never crosses a row
   // or a chunk's edge).  Work unit j: row j / W4 of the item, columns
-  // 4 (j mod W4) .. +3; kGroups units per thread in flight together for
-  // each chunk.
+  // 4 (j mod W4) .. +3; a thread holds kGroups units and loads them from
+  // kQ chunks at a time (a chunk that does not cover a unit adds zero).
   {
-    constexpr int kGroups = 4;
+    constexpr int kGroups = 3, kQ = 2;
     const int W4 = W >> 2;
     const int n4 = 2 * npair * W4;
     const unsigned m_w4 = div_magic(W4);
@@ -260,23 +257,30 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
         rr[g] = div_small(j, m_w4);
         cc[g] = 4 * (j - rr[g] * W4);
       }
-      for (int q = q0; q < q1; ++q) {
-        const int2 cq = L.chunk_col[q];
-        const float* part = G.Hp + L.chunk_hp[q] + static_cast<size_t>(r0) * cq.y;
-        float4 v[kGroups];
+      for (int q = q0; q < q1; q += kQ) {
+        float4 v[kQ][kGroups];
 #pragma unroll
-        for (int g = 0; g < kGroups; ++g) {
-          const int c = cc[g] - cq.x;
-          v[g] = (j0 + g * kNtBand < n4 && c >= 0 && c < cq.y)
-                     ? *reinterpret_cast<const float4*>(part + rr[g] * cq.y + c)
-                     : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int s = 0; s < kQ; ++s) {
+          const bool has = q + s < q1;
+          const int2 cq = has ? L.chunk_col[q + s] : make_int2(0, 0);
+          const float* part = G.Hp + (has ? L.chunk_hp[q + s] : 0) + static_cast<size_t>(r0) * cq.y;
+#pragma unroll
+          for (int g = 0; g < kGroups; ++g) {
+            const int c = cc[g] - cq.x;
+            v[s][g] = (j0 + g * kNtBand < n4 && c >= 0 && c < cq.y)
+                          ? *reinterpret_cast<const float4*>(part + rr[g] * cq.y + c)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
         }
 #pragma unroll
-        for (int g = 0; g < kGroups; ++g) {
-          acc[g].x += v[g].x;
-          acc[g].y += v[g].y;
-          acc[g].z += v[g].z;
-          acc[g].w += v[g].w;
+        for (int s = 0; s < kQ; ++s) {
+#pragma unroll
+          for (int g = 0; g < kGroups; ++g) {
+            acc[g].x += v[s][g].x;
+            acc[g].y += v[s][g].y;
+            acc[g].z += v[s][g].z;
+            acc[g].w += v[s][g].w;
+          }
         }
       }
 #pragma unroll
@@ -286,7 +290,7 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowfft(DevGeo one,
           float* dst = ldsf + 2 * ((r >> 1) * SP) + (r & 1);
           const float a[4] = {acc[g].x, acc[g].y, acc[g].z, acc[g].w};
 #pragma unroll
-          for (int t = 0; t < 4; ++t) dst[2 * lpad(G.xw0 + cc[g] + t)] = a[t] + bad;
+          for (int t = 0; t < 4; ++t) dst[2 * lpad(G.xw0 + cc[g] + t)] = a[t];
         }
       }
     }
@@ -419,26 +423,44 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo one,
   const int nr = min(G.row_rows, G.u1 - n0);
   const int npair = nr >> 1;
   const int Mt = G.Mt, SP = padded_len(G.Mt), W = G.W;
-  for (int i = threadIdx.x; i < npair * SP; i += kNtBand) lds[i] = make_float2(0.f, 0.f);
-  __syncthreads();
+  // the half spectra k < K1 of both rows of each pair (and through them
+  // the pair's spectrum at Mt - k) come from S; the frequencies K1 .. Mt - K1
+  // in between are zero.  The loads of the first group are issued before the
+  // zero fill, which touches other slots, so one barrier closes both.
   const int psh = pair_shift(npair);
-  grouped_for<kNtBand, 4>(
-      G.K1 << psh,
-      [&](int idx) {
-        const int k = idx >> psh;
-        const int p = idx & ((1 << psh) - 1);
-        return p < npair ? *reinterpret_cast<const float4*>(G.S + static_cast<size_t>(k) * G.Mr +
-                                                            n0 + 2 * p)
-                         : make_float4(0.f, 0.f, 0.f, 0.f);
-      },
-      [&](int idx, float4 x) {
-        const int k = idx >> psh;
-        const int p = idx & ((1 << psh) - 1);
-        if (p >= npair) return;
+  const int nk = G.K1 << psh;
+  constexpr int kG = 4;
+  for (int i0 = threadIdx.x; i0 < nk || i0 == static_cast<int>(threadIdx.x); i0 += kNtBand * kG) {
+    float4 x[kG];
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      const int idx = i0 + g * kNtBand;
+      const int k = idx >> psh;
+      const int p = idx & ((1 << psh) - 1);
+      x[g] = (idx < nk && p < npair)
+                 ? *reinterpret_cast<const float4*>(G.S + static_cast<size_t>(k) * G.Mr + n0 + 2 * p)
+                 : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (i0 == static_cast<int>(threadIdx.x)) {
+      const int gap = Mt - 2 * G.K1 + 1;  // frequencies K1 .. Mt - K1
+      const unsigned m_gap = div_magic(gap);
+      for (int i = threadIdx.x; i < npair * gap; i += kNtBand) {
+        const int p = div_small(i, m_gap);
+        lds[p * SP + lpad(G.K1 + i - p * gap)] = make_float2(0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      const int idx = i0 + g * kNtBand;
+      const int k = idx >> psh;
+      const int p = idx & ((1 << psh) - 1);
+      if (idx < nk && p < npair) {
         // X1 = (x.x, x.y), X2 = (x.z, x.w)
-        lds[p * SP + lpad(k)] = make_float2(x.x - x.w, x.y + x.z);
-        if (k > 0) lds[p * SP + lpad(Mt - k)] = make_float2(x.x + x.w, x.z - x.y);
-      });
+        lds[p * SP + lpad(k)] = make_float2(x[g].x - x[g].w, x[g].y + x[g].z);
+        if (k > 0) lds[p * SP + lpad(Mt - k)] = make_float2(x[g].x + x[g].w, x[g].z - x[g].y);
+      }
+    }
+  }
   __syncthreads();
   fft_rows<kNtBand, kInplaceValues, true>(lds, SP, npair,
                                           fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
