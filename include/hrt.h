@@ -36,6 +36,9 @@
  *    never synchronize the host, and overwrite their output completely.
  *  - A plan may be used by one stream at a time; distinct plans are
  *    independent.  Device faults surface as HRT_ERR_HIP on a later call.
+ *  - A NaN or infinity anywhere in a transform's input makes its whole
+ *    output NaN (the adjoint's: every sample inside the trapezoid); within
+ *    a batch, only the output of the gather that holds it.
  */
 #ifndef HRT_H_
 #define HRT_H_

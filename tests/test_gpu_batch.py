@@ -161,3 +161,34 @@ def test_batch_ista_graph_replays_match_eager():
     for i, d in enumerate(descs):
         assert b.opnorm2(i, iters=10) == Plan(d).opnorm2(iters=10)
     b.close()
+
+
+def test_non_finite_member_stays_in_its_gather():
+    """A NaN or inf in one gather of a batch makes that gather's output NaN
+    everywhere (its own input maximum fails, its spread chunks write NaN
+    partials) and leaves the other gathers equal to their single calls."""
+    from paper_1604_07651_amd.hrt import Batch, Plan
+    descs = DESCS[:3]
+    b = Batch(descs)
+    pairs = [synth.random_pair(d, 90 + i, dtype=np.float32) for i, d in enumerate(descs)]
+    keep = logpolar.LogPolarOracle(descs[1]).geo.keep
+    for bad in (float("nan"), float("inf")):
+        fs = [p[0].copy() for p in pairs]
+        gs = [p[1].copy() for p in pairs]
+        fs[1][3, 5] = bad
+        gs[1][2, 4] = bad
+        print(f"[gpu] batch with {bad} in gather 1", flush=True)
+        gb = b.unpack_radon(b.forward(b.pack_data(fs)))
+        fb = b.unpack_data(b.adjoint(b.pack_radon(gs)))
+        torch.cuda.synchronize()
+        assert torch.isnan(gb[1]).all()
+        assert torch.isnan(fb[1][torch.from_numpy(keep).cuda()]).all()
+        for i in (0, 2):
+            plan = Plan(descs[i])
+            g1 = plan.forward(torch.from_numpy(fs[i]).cuda())
+            f1 = plan.adjoint(torch.from_numpy(gs[i]).cuda())
+            torch.cuda.synchronize()
+            assert torch.equal(gb[i], g1)
+            assert torch.equal(fb[i], f1)
+            plan.close()
+    b.close()
