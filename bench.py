@@ -10,7 +10,8 @@ offsets (0..4 km) -> Radon panel 2048 taus x 1024 slownesses (v in
 (oversampling 2).  Prints one JSON line.
 
 Beside the throughput it reports: per-kernel HIP-event timings and the HBM
-roofline of the dominant kernel, the float32 GPU direct summation over
+roofline of the dominant kernel (the adjoint spread; its rate of 64-bit LDS
+atomic adds beside it, the unit that bounds it), the float32 GPU direct summation over
 hyperbolas (the paper's reference method) on the same gather, the rel-L2 of
 both directions against the FP64 oracle, and the FP64 oracle itself timed on
 the host cores.
@@ -660,6 +661,13 @@ def main():
     achieved = kernels[dom]["gbs"]
     dom_kernel = STAGE_KERNELS[list(kernels).index(dom)]
     traffic = stored_traffic(dom_kernel)
+    # the adjoint spread adds 16 taps (64-bit LDS atomics) per non-zero Radon
+    # sample; its input is the forward's output of the timed steps
+    adj_taps = 16 * int(torch.count_nonzero(g).item())
+    adj_us = kernels["adj_spread"]["avg_us"] if "adj_spread" in kernels else None
+    spread_atomics = {"kernel": "k_spread<1, false>", "taps_per_launch": adj_taps,
+                      "avg_us": adj_us,
+                      "g_adds_per_s": round(adj_taps / (adj_us * 1e-6) / 1e9, 1) if adj_us else None}
 
     # reference method on the GPU: direct summation over hyperbolas
     log("GPU direct summation")
@@ -716,6 +724,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
+        "spread_atomics": spread_atomics,
         "kernels": kernels,
         "kernel_source_hash": kernel_source_hash(),
         "per_step": {"plan_s": round(plan_sec, 3), "ms_fwd": round(lp_fwd_sec * 1e3, 5),
