@@ -367,14 +367,16 @@ def test_unaligned_input_matches_aligned():
 VARIANT_FLAGS = list(range(1, 8)) + [8, 16, 32, 64, 8 | 32, 16 | 64, 16 | 4 | 32, 8 | 3 | 64]
 
 
-@pytest.mark.parametrize("flags", VARIANT_FLAGS)
-@pytest.mark.parametrize("name", ["ragged", "c2"])
+# (the FFT-only variants, flags below 8, on the ragged grid only)
+VARIANT_CASES = ([("ragged", fl) for fl in VARIANT_FLAGS]
+                 + [("c2", fl) for fl in VARIANT_FLAGS if fl >= 8])
+
+
+@pytest.mark.parametrize("name,flags", VARIANT_CASES)
 def test_kernel_variants_match_oracle(name, flags):
     """Every kernel variant against the oracle, to the same bar as the
     default; the plan's band height is the one the flags ask for."""
     from paper_1604_07651_amd.hrt import Plan
-    if name == "c2" and flags < 8:
-        pytest.skip("FFT-only variants are covered on the ragged grid")
     desc, _, ora = setup(name)
     plan = Plan(desc, flags=flags)
     want_rows = 2 if flags & 16 else 4 if flags & 8 else 8
