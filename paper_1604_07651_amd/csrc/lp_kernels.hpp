@@ -108,14 +108,13 @@ __global__ __launch_bounds__(256) void k_absmax(DevGeo one, const DevGeo* __rest
     G.absmax[w.i] = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
 }
 
-// The spread's fixed-point scale (float64): every accumulated cell and
+// The spread's fixed-point scale (float64) from each thread's maximum over
+// its share of the input maximum's partials: every accumulated cell and
 // every tap stays within 2^50 (cmax bounds a cell per unit of input, and a
 // single tap by as much); 0 for an all-zero or non-finite input (the latter
-// is reported through `finite`).
-__device__ __forceinline__ double spread_scale(const DevGeo& G, float cmax, float* s_wave,
+// is reported through `finite`).  Ends with a barrier.
+__device__ __forceinline__ double spread_scale(float vmax, float cmax, float* s_wave,
                                                bool& finite) {
-  float vmax = 0.0f;
-  for (int i = threadIdx.x; i < G.absmax_blocks; i += kNtBand) vmax = fmaxf(vmax, G.absmax[i]);
   vmax = block_max(vmax, s_wave);
   finite = vmax <= 3.0e38f;  // false for inf and NaN
   return (vmax > 0.0f && finite)
@@ -149,10 +148,22 @@ __global__ __launch_bounds__(kNtBand) void k_spread(DevGeo one, const DevGeo* __
   const int2 cols = L.chunk_col[chunk];  // {c_lo, wc}
   const int wc = cols.y;
   unsigned long long* acc = lds_q;
-  bool finite;
-  const double scale = spread_scale(G, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave, finite);
+  // the input maximum's partials are loaded first and the accumulator is
+  // cleared while they arrive; the scale's barriers also close the clearing
+  constexpr int kPre = 4;
+  float pre[kPre];
+#pragma unroll
+  for (int k = 0; k < kPre; ++k) {
+    const int i = threadIdx.x + k * kNtBand;
+    pre[k] = i < G.absmax_blocks ? G.absmax[i] : 0.0f;
+  }
   for (int i = threadIdx.x; i < nr * wc; i += kNtBand) acc[i] = 0ull;
-  __syncthreads();
+  float vpart = fmaxf(fmaxf(pre[0], pre[1]), fmaxf(pre[2], pre[3]));
+  for (int i = threadIdx.x + kPre * kNtBand; i < G.absmax_blocks; i += kNtBand)
+    vpart = fmaxf(vpart, G.absmax[i]);
+  bool finite;
+  const double scale =
+      spread_scale(vpart, MODE == 0 ? G.cmax_data : G.cmax_radon, s_wave, finite);
   if (scale > 0.0) {
     const int64_t e0 = L.chunk_off[chunk], e1 = L.chunk_off[chunk + 1];
     // the chunk is taken kNtBand entries at a time, thread t doing entry

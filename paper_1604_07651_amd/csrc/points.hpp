@@ -47,18 +47,18 @@ __device__ __forceinline__ void spread_taps(unsigned long long* acc, int wc, int
   }
 }
 
-// Maximum over the workgroup (kNtBand threads; s_wave holds kNtBand/64 floats).
+// Maximum over the workgroup (kNtBand threads; s_wave holds kNtBand/64
+// floats and is used once per kernel, so one barrier suffices; it also
+// orders every thread's earlier LDS writes before the return).
 __device__ __forceinline__ float block_max(float v, float* s_wave) {
   constexpr int kWaves = kNtBand / 64;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  __syncthreads();
   if ((threadIdx.x & 63) == 0) s_wave[threadIdx.x >> 6] = v;
   __syncthreads();
   float m = s_wave[0];
 #pragma unroll
   for (int i = 1; i < kWaves; ++i) m = fmaxf(m, s_wave[i]);
-  __syncthreads();
   return m;
 }
 
