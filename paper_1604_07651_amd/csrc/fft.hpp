@@ -287,14 +287,22 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, in
   }
 }
 
+// A pass's outputs as they are: the default of the passes' `post` hook.
+struct NoPost {
+  __device__ __forceinline__ void operator()(int, int, float2&) const {}
+};
+
 // In-place form of the same pass for a batch small enough that every thread
 // can hold all of its butterflies at once (U*R <= VALUES; the plan checks
 // ceil(B*n/R / NT) <= VALUES/R for every radix): all loads, a
 // barrier, then twiddles, DFTs and stores into the same buffer.  It needs no
 // scratch, so a workgroup takes half the LDS of the ping-pong form.
-template <int R, int NT, int VALUES, bool INV>
+// post(u, r, value) sees output r of the thread's butterfly u just before
+// its store (u, r compile-time constants once unrolled).
+template <int R, int NT, int VALUES, bool INV, class Post = NoPost>
 __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, int B, int Ns,
-                                             const float2* __restrict__ tw) {
+                                             const float2* __restrict__ tw,
+                                             const Post& post = Post()) {
   constexpr int U = inplace_units(R, VALUES);
   constexpr int NB2 = R > 8 ? 4 : (R > 4 ? 3 : (R > 2 ? 2 : 1));
   const int nb = n / R;
@@ -347,10 +355,52 @@ __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, in
       }
       Dft<R, INV>::run(v[u]);
 #pragma unroll
-      for (int r = 0; r < R; ++r) data[ob[u] + lpad(oo[u] + r * Ns)] = v[u][r];
+      for (int r = 0; r < R; ++r) {
+        post(u, r, v[u][r]);
+        data[ob[u] + lpad(oo[u] + r * Ns)] = v[u][r];
+      }
     }
   }
   __syncthreads();
+}
+
+// One sequence in place with `post` applied to the last pass's outputs
+// (see inplace_pass).  The caller synchronises before the call; the call
+// ends synchronised.
+template <int NT, int VALUES, bool INV, class Post>
+__device__ __forceinline__ void fft_inplace_post(float2* data, const FftDev& f, const float2* __restrict__ tw,
+                                 const Post& post) {
+  const int n = f.n;
+  int Ns = 1;
+  for (int p = 0; p + 1 < f.npass; ++p) {
+    switch (fft_radix(f, p)) {
+      case 16: inplace_pass<16, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
+      case 15: inplace_pass<15, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
+      case 12: inplace_pass<12, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
+      case 10: inplace_pass<10, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
+      case 9: inplace_pass<9, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
+      case 8: inplace_pass<8, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
+      case 6: inplace_pass<6, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
+      case 5: inplace_pass<5, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
+      case 4: inplace_pass<4, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
+      case 3: inplace_pass<3, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
+      default: inplace_pass<2, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
+    }
+    Ns *= fft_radix(f, p);
+  }
+  switch (fft_radix(f, f.npass - 1)) {
+    case 16: inplace_pass<16, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
+    case 15: inplace_pass<15, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
+    case 12: inplace_pass<12, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
+    case 10: inplace_pass<10, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
+    case 9: inplace_pass<9, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
+    case 8: inplace_pass<8, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
+    case 6: inplace_pass<6, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
+    case 5: inplace_pass<5, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
+    case 4: inplace_pass<4, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
+    case 3: inplace_pass<3, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
+    default: inplace_pass<2, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
+  }
 }
 
 // Transform B sequences at data + b*stride in place, `group` sequences at a

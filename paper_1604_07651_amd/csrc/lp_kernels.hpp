@@ -386,24 +386,40 @@ __global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo one, const DevGeo* 
   }
   __syncthreads();
   float2* cscr = G.col_inplace ? nullptr : lds + SP;
-  fft_rows<kNtCol, kInplaceValues, false>(lds, SP, nc, cscr, nc, G.fr, s_tw);
-  if (kpre) {
-#pragma unroll
-    for (int g = 0; g < kKRegs; ++g) {
-      const int n = static_cast<int>(threadIdx.x) + g * kNtCol;
-      float2 kv = kr[g];
-      if ((n >= Mr / 2) != ADJ) kv.y = -kv.y;  // as in kval: k2 < 0 takes conj K
-      if (n < Mr) kmul(lds, n, kv);
-    }
+  // where the forward FFT's last pass gives thread t exactly the outputs
+  // t + r kNtCol (one butterfly per thread over all kNtCol threads), the
+  // multiply by K is done on them before they are stored (their K values
+  // are the thread's registers kr[r])
+  const bool fused = kpre && cscr == nullptr && Mr == kNtCol * fft_radix(G.fr, G.fr.npass - 1);
+  if (fused) {
+    fft_inplace_post<kNtCol, kInplaceValues, false>(
+        lds, G.fr, s_tw, [&](int, int r, float2& x) {
+          const int n = static_cast<int>(threadIdx.x) + r * kNtCol;
+          float2 kv = kr[r];
+          if ((n >= Mr / 2) != ADJ) kv.y = -kv.y;  // as in kval: k2 < 0 takes conj K
+          const int ak = n < Mr / 2 ? n : Mr - n;
+          x = ak < K2 ? cscale(cmul(x, kv), G.knorm) : make_float2(0.f, 0.f);
+        });
   } else {
-    for (int c = 0; c < nc; ++c) {
-      const float2* kc = G.K + static_cast<size_t>(c0 + c) * K2;
-      float2* lc = lds + c * SP;
-      grouped_for<kNtCol, 8>(
-          Mr, [&](int n) { return kval(kc, n); }, [&](int n, float2 kv) { kmul(lc, n, kv); });
+    fft_rows<kNtCol, kInplaceValues, false>(lds, SP, nc, cscr, nc, G.fr, s_tw);
+    if (kpre) {
+#pragma unroll
+      for (int g = 0; g < kKRegs; ++g) {
+        const int n = static_cast<int>(threadIdx.x) + g * kNtCol;
+        float2 kv = kr[g];
+        if ((n >= Mr / 2) != ADJ) kv.y = -kv.y;  // as in kval: k2 < 0 takes conj K
+        if (n < Mr) kmul(lds, n, kv);
+      }
+    } else {
+      for (int c = 0; c < nc; ++c) {
+        const float2* kc = G.K + static_cast<size_t>(c0 + c) * K2;
+        float2* lc = lds + c * SP;
+        grouped_for<kNtCol, 8>(
+            Mr, [&](int n) { return kval(kc, n); }, [&](int n, float2 kv) { kmul(lc, n, kv); });
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
   fft_rows<kNtCol, kInplaceValues, true>(lds, SP, nc, cscr, nc, G.fr, s_tw);
   for (int c = 0; c < nc; ++c) {
     float2* col = S + static_cast<size_t>(c0 + c) * Mr + u0;
