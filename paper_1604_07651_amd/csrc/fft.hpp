@@ -288,17 +288,34 @@ __device__ __forceinline__ void stockham_pass(const float2* __restrict__ src, in
 }
 
 // A pass's outputs as they are: the default of the passes' `post` hook.
+// A hook sees (sequence b, output index, unrolled output r of the thread's
+// butterfly, value) before the value is stored; with kStores the hook
+// stores the value itself and the pass leaves LDS as it was.
 struct NoPost {
-  __device__ __forceinline__ void operator()(int, int, float2&) const {}
+  static constexpr bool kStores = false;
+  __device__ __forceinline__ void operator()(int, int, int, float2&) const {}
 };
+
+// A hook from a callable f(b, index, r, value&).
+template <bool STORES, class F>
+struct PostFn {
+  static constexpr bool kStores = STORES;
+  F f;
+  __device__ __forceinline__ void operator()(int b, int i, int r, float2& v) const { f(b, i, r, v); }
+};
+template <bool STORES, class F>
+__device__ __forceinline__ PostFn<STORES, F> make_post(F f) {
+  return PostFn<STORES, F>{f};
+}
 
 // In-place form of the same pass for a batch small enough that every thread
 // can hold all of its butterflies at once (U*R <= VALUES; the plan checks
 // ceil(B*n/R / NT) <= VALUES/R for every radix): all loads, a
 // barrier, then twiddles, DFTs and stores into the same buffer.  It needs no
 // scratch, so a workgroup takes half the LDS of the ping-pong form.
-// post(u, r, value) sees output r of the thread's butterfly u just before
-// its store (u, r compile-time constants once unrolled).
+// post(b, index, r, value) sees output r of the thread's butterfly (r a
+// compile-time constant once unrolled), output `index` of sequence b, just
+// before its store (see NoPost).
 template <int R, int NT, int VALUES, bool INV, class Post = NoPost>
 __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, int B, int Ns,
                                              const float2* __restrict__ tw,
@@ -311,7 +328,7 @@ __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, in
   const int nhi = (n + 63) >> 6;
   const unsigned m_nb = div_magic(nb), m_ns = div_magic(Ns);
   float2 v[U][R];
-  int ob[U], oo[U], kk[U];
+  int ob[U], oo[U], kk[U], bq[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int idx = threadIdx.x + u * NT;
@@ -319,6 +336,7 @@ __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, in
     const int j = idx - b * nb;
     const int k = j - div_small(j, m_ns) * Ns;
     kk[u] = k;
+    bq[u] = b;
     ob[u] = b * stride;
     oo[u] = (j - k) * R + k;
     if (idx < total) {
@@ -356,50 +374,52 @@ __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, in
       Dft<R, INV>::run(v[u]);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        post(u, r, v[u][r]);
-        data[ob[u] + lpad(oo[u] + r * Ns)] = v[u][r];
+        post(bq[u], oo[u] + r * Ns, r, v[u][r]);
+        if (!Post::kStores) data[ob[u] + lpad(oo[u] + r * Ns)] = v[u][r];
       }
     }
   }
   __syncthreads();
 }
 
-// One sequence in place with `post` applied to the last pass's outputs
-// (see inplace_pass).  The caller synchronises before the call; the call
-// ends synchronised.
+// B sequences at data + b*stride in place, all in one group (see
+// inplace_pass for the size condition), with `post` applied to the last
+// pass's outputs.  The caller synchronises before the call; the call ends
+// synchronised.
 template <int NT, int VALUES, bool INV, class Post>
-__device__ __forceinline__ void fft_inplace_post(float2* data, const FftDev& f, const float2* __restrict__ tw,
-                                 const Post& post) {
+__device__ __forceinline__ void fft_inplace_post(float2* data, int stride, int B, const FftDev& f,
+                                                 const float2* __restrict__ tw,
+                                                 const Post& post) {
   const int n = f.n;
   int Ns = 1;
   for (int p = 0; p + 1 < f.npass; ++p) {
     switch (fft_radix(f, p)) {
-      case 16: inplace_pass<16, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
-      case 15: inplace_pass<15, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
-      case 12: inplace_pass<12, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
-      case 10: inplace_pass<10, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
-      case 9: inplace_pass<9, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
-      case 8: inplace_pass<8, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
-      case 6: inplace_pass<6, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
-      case 5: inplace_pass<5, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
-      case 4: inplace_pass<4, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
-      case 3: inplace_pass<3, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
-      default: inplace_pass<2, NT, VALUES, INV>(data, 0, n, 1, Ns, tw); break;
+      case 16: inplace_pass<16, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
+      case 15: inplace_pass<15, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
+      case 12: inplace_pass<12, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
+      case 10: inplace_pass<10, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
+      case 9: inplace_pass<9, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
+      case 8: inplace_pass<8, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
+      case 6: inplace_pass<6, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
+      case 5: inplace_pass<5, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
+      case 4: inplace_pass<4, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
+      case 3: inplace_pass<3, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
+      default: inplace_pass<2, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
     }
     Ns *= fft_radix(f, p);
   }
   switch (fft_radix(f, f.npass - 1)) {
-    case 16: inplace_pass<16, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
-    case 15: inplace_pass<15, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
-    case 12: inplace_pass<12, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
-    case 10: inplace_pass<10, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
-    case 9: inplace_pass<9, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
-    case 8: inplace_pass<8, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
-    case 6: inplace_pass<6, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
-    case 5: inplace_pass<5, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
-    case 4: inplace_pass<4, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
-    case 3: inplace_pass<3, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
-    default: inplace_pass<2, NT, VALUES, INV>(data, 0, n, 1, Ns, tw, post); break;
+    case 16: inplace_pass<16, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
+    case 15: inplace_pass<15, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
+    case 12: inplace_pass<12, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
+    case 10: inplace_pass<10, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
+    case 9: inplace_pass<9, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
+    case 8: inplace_pass<8, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
+    case 6: inplace_pass<6, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
+    case 5: inplace_pass<5, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
+    case 4: inplace_pass<4, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
+    case 3: inplace_pass<3, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
+    default: inplace_pass<2, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
   }
 }
 

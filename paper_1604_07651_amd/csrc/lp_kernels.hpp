@@ -393,13 +393,12 @@ __global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo one, const DevGeo* 
   const bool fused = kpre && cscr == nullptr && Mr == kNtCol * fft_radix(G.fr, G.fr.npass - 1);
   if (fused) {
     fft_inplace_post<kNtCol, kInplaceValues, false>(
-        lds, G.fr, s_tw, [&](int, int r, float2& x) {
-          const int n = static_cast<int>(threadIdx.x) + r * kNtCol;
-          float2 kv = kr[r];
+        lds, SP, 1, G.fr, s_tw, make_post<false>([&](int, int n, int r, float2& x) {
+          float2 kv = kr[r];  // n = threadIdx.x + r * kNtCol
           if ((n >= Mr / 2) != ADJ) kv.y = -kv.y;  // as in kval: k2 < 0 takes conj K
           const int ak = n < Mr / 2 ? n : Mr - n;
           x = ak < K2 ? cscale(cmul(x, kv), G.knorm) : make_float2(0.f, 0.f);
-        });
+        }));
   } else {
     fft_rows<kNtCol, kInplaceValues, false>(lds, SP, nc, cscr, nc, G.fr, s_tw);
     if (kpre) {
@@ -419,6 +418,15 @@ __global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo one, const DevGeo* 
       }
     }
     __syncthreads();
+  }
+  if (fused) {
+    // the inverse's last pass stores the used rows straight to S
+    float2* col = S + static_cast<size_t>(c0) * Mr;
+    fft_inplace_post<kNtCol, kInplaceValues, true>(
+        lds, SP, 1, G.fr, s_tw, make_post<true>([&](int, int n, int, float2& x) {
+          if (n >= u0 && n < u0 + U) col[n] = x;
+        }));
+    return;
   }
   fft_rows<kNtCol, kInplaceValues, true>(lds, SP, nc, cscr, nc, G.fr, s_tw);
   for (int c = 0; c < nc; ++c) {
@@ -489,10 +497,24 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo one,
     }
   }
   __syncthreads();
+  float* dst = G.Cr + static_cast<size_t>(n0 - G.u0) * W;
+  if (G.row_scratch < 0 && G.row_group >= npair) {
+    // all pairs in place at once: the last pass stores the window columns of
+    // both rows of each pair straight to Cr
+    fft_inplace_post<kNtBand, kInplaceValues, true>(
+        lds, SP, npair, G.ft, s_tw, make_post<true>([&](int p, int m, int, float2& z) {
+          const int c = m - G.xw0;
+          if (c >= 0 && c < W) {
+            float* d = dst + (2 * p) * W;
+            d[c] = z.x;
+            d[W + c] = z.y;
+          }
+        }));
+    return;
+  }
   fft_rows<kNtBand, kInplaceValues, true>(lds, SP, npair,
                                           fft_scratch(reinterpret_cast<char*>(lds), G.row_scratch),
                                           G.row_group, G.ft, s_tw);
-  float* dst = G.Cr + static_cast<size_t>(n0 - G.u0) * W;
   for (int p = 0; p < npair; ++p) {
     const float2* lp = lds + p * SP;
     float* d = dst + (2 * p) * W;
