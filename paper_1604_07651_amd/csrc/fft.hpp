@@ -296,6 +296,24 @@ struct NoPost {
   __device__ __forceinline__ void operator()(int, int, int, float2&) const {}
 };
 
+// The first pass's inputs as they are in LDS: the default of the passes'
+// `pre` hook.  A hook with kLoads gives input `index` of sequence b itself
+// (from global memory, say), and the pass reads no LDS.
+struct NoPre {
+  static constexpr bool kLoads = false;
+  __device__ __forceinline__ float2 operator()(int, int) const { return make_float2(0.f, 0.f); }
+};
+template <class F>
+struct PreFn {
+  static constexpr bool kLoads = true;
+  F f;
+  __device__ __forceinline__ float2 operator()(int b, int i) const { return f(b, i); }
+};
+template <class F>
+__device__ __forceinline__ PreFn<F> make_pre(F f) {
+  return PreFn<F>{f};
+}
+
 // A hook from a callable f(b, index, r, value&).
 template <bool STORES, class F>
 struct PostFn {
@@ -316,10 +334,10 @@ __device__ __forceinline__ PostFn<STORES, F> make_post(F f) {
 // post(b, index, r, value) sees output r of the thread's butterfly (r a
 // compile-time constant once unrolled), output `index` of sequence b, just
 // before its store (see NoPost).
-template <int R, int NT, int VALUES, bool INV, class Post = NoPost>
+template <int R, int NT, int VALUES, bool INV, class Post = NoPost, class Pre = NoPre>
 __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, int B, int Ns,
                                              const float2* __restrict__ tw,
-                                             const Post& post = Post()) {
+                                             const Post& post = Post(), const Pre& pre = Pre()) {
   constexpr int U = inplace_units(R, VALUES);
   constexpr int NB2 = R > 8 ? 4 : (R > 4 ? 3 : (R > 2 ? 2 : 1));
   const int nb = n / R;
@@ -342,7 +360,7 @@ __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, in
     if (idx < total) {
       const float2* in = data + b * stride;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[u][r] = in[lpad(j + r * nb)];
+      for (int r = 0; r < R; ++r) v[u][r] = Pre::kLoads ? pre(b, j + r * nb) : in[lpad(j + r * nb)];
     }
   }
   __syncthreads();
@@ -382,45 +400,46 @@ __device__ __forceinline__ void inplace_pass(float2* data, int stride, int n, in
   __syncthreads();
 }
 
+// One in-place pass of the radix `R` (runtime) with the given hooks.
+template <int NT, int VALUES, bool INV, class Pre, class Post>
+__device__ __forceinline__ void hooked_pass(int R, float2* data, int stride, int n, int B, int Ns,
+                                            const float2* __restrict__ tw, const Pre& pre,
+                                            const Post& post) {
+  switch (R) {
+    case 16: inplace_pass<16, NT, VALUES, INV, Post, Pre>(data, stride, n, B, Ns, tw, post, pre); break;
+    case 15: inplace_pass<15, NT, VALUES, INV, Post, Pre>(data, stride, n, B, Ns, tw, post, pre); break;
+    case 12: inplace_pass<12, NT, VALUES, INV, Post, Pre>(data, stride, n, B, Ns, tw, post, pre); break;
+    case 10: inplace_pass<10, NT, VALUES, INV, Post, Pre>(data, stride, n, B, Ns, tw, post, pre); break;
+    case 9: inplace_pass<9, NT, VALUES, INV, Post, Pre>(data, stride, n, B, Ns, tw, post, pre); break;
+    case 8: inplace_pass<8, NT, VALUES, INV, Post, Pre>(data, stride, n, B, Ns, tw, post, pre); break;
+    case 6: inplace_pass<6, NT, VALUES, INV, Post, Pre>(data, stride, n, B, Ns, tw, post, pre); break;
+    case 5: inplace_pass<5, NT, VALUES, INV, Post, Pre>(data, stride, n, B, Ns, tw, post, pre); break;
+    case 4: inplace_pass<4, NT, VALUES, INV, Post, Pre>(data, stride, n, B, Ns, tw, post, pre); break;
+    case 3: inplace_pass<3, NT, VALUES, INV, Post, Pre>(data, stride, n, B, Ns, tw, post, pre); break;
+    default: inplace_pass<2, NT, VALUES, INV, Post, Pre>(data, stride, n, B, Ns, tw, post, pre); break;
+  }
+}
+
 // B sequences at data + b*stride in place, all in one group (see
-// inplace_pass for the size condition), with `post` applied to the last
-// pass's outputs.  The caller synchronises before the call; the call ends
-// synchronised.
-template <int NT, int VALUES, bool INV, class Post>
-__device__ __forceinline__ void fft_inplace_post(float2* data, int stride, int B, const FftDev& f,
-                                                 const float2* __restrict__ tw,
-                                                 const Post& post) {
-  const int n = f.n;
-  int Ns = 1;
-  for (int p = 0; p + 1 < f.npass; ++p) {
-    switch (fft_radix(f, p)) {
-      case 16: inplace_pass<16, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
-      case 15: inplace_pass<15, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
-      case 12: inplace_pass<12, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
-      case 10: inplace_pass<10, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
-      case 9: inplace_pass<9, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
-      case 8: inplace_pass<8, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
-      case 6: inplace_pass<6, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
-      case 5: inplace_pass<5, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
-      case 4: inplace_pass<4, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
-      case 3: inplace_pass<3, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
-      default: inplace_pass<2, NT, VALUES, INV>(data, stride, n, B, Ns, tw); break;
-    }
+// inplace_pass for the size condition), the first pass's inputs from `pre`
+// and the last pass's outputs through `post` (see NoPre, NoPost).  The
+// caller synchronises before the call; the call ends synchronised.
+template <int NT, int VALUES, bool INV, class Pre, class Post>
+__device__ __forceinline__ void fft_inplace_hooks(float2* data, int stride, int B, const FftDev& f,
+                                                  const float2* __restrict__ tw, const Pre& pre,
+                                                  const Post& post) {
+  const int n = f.n, last = f.npass - 1;
+  if (last == 0) {
+    hooked_pass<NT, VALUES, INV>(fft_radix(f, 0), data, stride, n, B, 1, tw, pre, post);
+    return;
+  }
+  hooked_pass<NT, VALUES, INV>(fft_radix(f, 0), data, stride, n, B, 1, tw, pre, NoPost());
+  int Ns = fft_radix(f, 0);
+  for (int p = 1; p < last; ++p) {
+    hooked_pass<NT, VALUES, INV>(fft_radix(f, p), data, stride, n, B, Ns, tw, NoPre(), NoPost());
     Ns *= fft_radix(f, p);
   }
-  switch (fft_radix(f, f.npass - 1)) {
-    case 16: inplace_pass<16, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
-    case 15: inplace_pass<15, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
-    case 12: inplace_pass<12, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
-    case 10: inplace_pass<10, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
-    case 9: inplace_pass<9, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
-    case 8: inplace_pass<8, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
-    case 6: inplace_pass<6, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
-    case 5: inplace_pass<5, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
-    case 4: inplace_pass<4, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
-    case 3: inplace_pass<3, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
-    default: inplace_pass<2, NT, VALUES, INV>(data, stride, n, B, Ns, tw, post); break;
-  }
+  hooked_pass<NT, VALUES, INV>(fft_radix(f, last), data, stride, n, B, Ns, tw, NoPre(), post);
 }
 
 // Transform B sequences at data + b*stride in place, `group` sequences at a

@@ -376,24 +376,30 @@ __global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo one, const DevGeo* 
       kr[g] = kc[min(ak, K2 - 1)];
     }
   }
-  for (int c = 0; c < nc; ++c) {
-    const float2* col = S + static_cast<size_t>(c0 + c) * Mr;
-    float2* lc = lds + c * SP;
-    grouped_for<kNtCol, 8>(
-        Mr,
-        [&](int n) { return (n >= u0 && n < u0 + U) ? col[n] : make_float2(0.f, 0.f); },
-        [&](int n, float2 v) { lc[lpad(n)] = v; });
-  }
-  __syncthreads();
   float2* cscr = G.col_inplace ? nullptr : lds + SP;
   // where the forward FFT's last pass gives thread t exactly the outputs
   // t + r kNtCol (one butterfly per thread over all kNtCol threads), the
   // multiply by K is done on them before they are stored (their K values
-  // are the thread's registers kr[r])
+  // are the thread's registers kr[r]); the first pass then also reads the
+  // column straight from S, and the inverse's last pass stores it there
   const bool fused = kpre && cscr == nullptr && Mr == kNtCol * fft_radix(G.fr, G.fr.npass - 1);
+  if (!fused) {
+    for (int c = 0; c < nc; ++c) {
+      const float2* col = S + static_cast<size_t>(c0 + c) * Mr;
+      float2* lc = lds + c * SP;
+      grouped_for<kNtCol, 8>(
+          Mr,
+          [&](int n) { return (n >= u0 && n < u0 + U) ? col[n] : make_float2(0.f, 0.f); },
+          [&](int n, float2 v) { lc[lpad(n)] = v; });
+    }
+    __syncthreads();
+  }
   if (fused) {
-    fft_inplace_post<kNtCol, kInplaceValues, false>(
-        lds, SP, 1, G.fr, s_tw, make_post<false>([&](int, int n, int r, float2& x) {
+    const float2* col = S + static_cast<size_t>(c0) * Mr;
+    fft_inplace_hooks<kNtCol, kInplaceValues, false>(
+        lds, SP, 1, G.fr, s_tw,
+        make_pre([&](int, int n) { return (n >= u0 && n < u0 + U) ? col[n] : make_float2(0.f, 0.f); }),
+        make_post<false>([&](int, int n, int r, float2& x) {
           float2 kv = kr[r];  // n = threadIdx.x + r * kNtCol
           if ((n >= Mr / 2) != ADJ) kv.y = -kv.y;  // as in kval: k2 < 0 takes conj K
           const int ak = n < Mr / 2 ? n : Mr - n;
@@ -422,8 +428,8 @@ __global__ __launch_bounds__(kNtCol, 2) void k_colfft(DevGeo one, const DevGeo* 
   if (fused) {
     // the inverse's last pass stores the used rows straight to S
     float2* col = S + static_cast<size_t>(c0) * Mr;
-    fft_inplace_post<kNtCol, kInplaceValues, true>(
-        lds, SP, 1, G.fr, s_tw, make_post<true>([&](int, int n, int, float2& x) {
+    fft_inplace_hooks<kNtCol, kInplaceValues, true>(
+        lds, SP, 1, G.fr, s_tw, NoPre(), make_post<true>([&](int, int n, int, float2& x) {
           if (n >= u0 && n < u0 + U) col[n] = x;
         }));
     return;
@@ -501,8 +507,8 @@ __global__ __launch_bounds__(kNtBand, 6) void k_rowifft(DevGeo one,
   if (G.row_scratch < 0 && G.row_group >= npair) {
     // all pairs in place at once: the last pass stores the window columns of
     // both rows of each pair straight to Cr
-    fft_inplace_post<kNtBand, kInplaceValues, true>(
-        lds, SP, npair, G.ft, s_tw, make_post<true>([&](int p, int m, int, float2& z) {
+    fft_inplace_hooks<kNtBand, kInplaceValues, true>(
+        lds, SP, npair, G.ft, s_tw, NoPre(), make_post<true>([&](int p, int m, int, float2& z) {
           const int c = m - G.xw0;
           if (c >= 0 && c < W) {
             float* d = dst + (2 * p) * W;
