@@ -60,7 +60,7 @@ SMALL = {
     # the paper's N = 2^12 grid of the size sweep, whole (dot test only)
     "s4096": synth.s1_desc(4096),
 }
-# log-radius axes of 256 x R points (R = 2, 3, 4, 5, 8, 9, 10, 15): the
+# log-radius axes of 256 x R points (R = 2, 3, 4, 5, 8, 9, 10, 15, 16): the
 # column pass's last forward radix R, whose outputs the multiply by K takes
 # in registers, and whose first pass reads the column from S (C2 and C3
 # cover R = 6, 12)
@@ -68,7 +68,8 @@ for _name, (_nt, _nx, _X, _qmax, _ov) in {
         "colr2": (400, 48, 1.0, 1 / 1.5, 2.0), "colr3": (1200, 24, 2.0, 1 / 1.5, 2.0),
         "colr4": (1000, 16, 0.5, 1 / 1.5, 2.0), "colr5": (1200, 32, 2.0, 0.5, 2.0),
         "colr8": (2000, 16, 0.5, 1 / 1.5, 2.0), "colr9": (2500, 24, 1.0, 2.0, 3.0),
-        "colr10": (2000, 16, 0.5, 1 / 1.5, 2.5), "colr15": (2500, 16, 0.5, 1 / 1.5, 3.0)}.items():
+        "colr10": (2000, 16, 0.5, 1 / 1.5, 2.5), "colr15": (2500, 16, 0.5, 1 / 1.5, 3.0),
+        "colr16": (2300, 16, 0.5, 1.0, 3.5)}.items():
     SMALL[_name] = synth.GridDesc(nt=_nt, nx=_nx, dt=0.004, x0=0.0, dx=_X / (_nx - 1), ntau=_nt,
                                   nq=_nx, tau0=0.0, dtau=0.004, q0=0.25,
                                   dq=(_qmax - 0.25) / (_nx - 1), oversample=_ov)
@@ -112,7 +113,7 @@ def test_kernel_multiplier_matches_oracle(name):
 @pytest.mark.parametrize("name", ["c1", "odd", "tiny", "ragged", "q0zero", "wide", "c2",
                                   "long", "ang4320", "ang8640", "min4", "nt4", "nx4",
                                   "colr2", "colr3", "colr4", "colr5", "colr8", "colr9",
-                                  "colr10", "colr15"])
+                                  "colr10", "colr15", "colr16"])
 @pytest.mark.parametrize("kind", ["random", "ricker"])
 def test_forward_and_adjoint_parity(name, kind):
     desc, plan, ora = setup(name)
