@@ -258,7 +258,7 @@ def ista_c5(torch, np, iters=100, mu_rel=0.01):
 def batch_c3(torch, np, n=8, reps=20):
     """n gathers of the C3 shape (drawn like C3, seeds 3 .. 3 + n - 1) in one
     batch: forward+adjoint of all of them with one launch per kernel, the
-    throughput of a survey's gathers taken n at a time (the headline value is
+    throughput of a seismic survey's gathers taken n at a time (the headline value is
     one gather per call)."""
     import synth
     from paper_1604_07651_amd.hrt import Batch
