@@ -6,7 +6,8 @@
 // a spread chunk's column range holds every stencil of its entries, stays
 // within the accumulator's width and the window, and its partial rows follow
 // the previous chunk's; the Radon entries of one slowness share their angle
-// coordinate and weight.  Grids with band heights 8, 4 and 2 are covered.
+// coordinate and weight.  Grids with band heights 8, 4 and 2 are covered,
+// and 24 seeded random grids.
 // Prints "ok" and exits 0, or prints the first failure and exits 1.
 #include <cmath>
 #include <cstdio>
@@ -208,6 +209,56 @@ static void run(const char* name, const hrt_desc& d, const PartView* view, int w
   }
 }
 
+// splitmix64: a seeded stream of 64-bit values for the random grids
+static uint64_t rng_state = 0x2026;
+static uint64_t next_u64() {
+  uint64_t z = (rng_state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+static double uniform(double lo, double hi) {
+  return lo + (hi - lo) * static_cast<double>(next_u64() >> 11) * 0x1.0p-53;
+}
+static int uniform_int(int lo, int hi) {  // [lo, hi)
+  return lo + static_cast<int>(next_u64() % static_cast<uint64_t>(hi - lo));
+}
+
+// Seeded random grids (sizes, steps, offsets, slowness ranges, oversampling
+// and the band/chunk variants all drawn at random); a grid the geometry
+// rejects is drawn again.
+static void run_random(int count) {
+  const uint32_t variants[] = {0u, HRT_TUNE_SPREAD_HALF, HRT_TUNE_GATHER_DOUBLE,
+                               HRT_TUNE_BAND4 | HRT_TUNE_SPREAD_HALF, HRT_TUNE_BAND2};
+  const double ovs[] = {1.5, 2.0, 2.5, 3.0};
+  const double dts[] = {0.002, 0.004, 0.008};
+  int done = 0;
+  while (done < count) {
+    hrt_desc d{};
+    d.nt = uniform_int(4, 600);
+    d.nx = uniform_int(4, 200);
+    d.dt = dts[uniform_int(0, 3)];
+    d.x0 = uniform_int(0, 2) ? 0.0 : uniform(0.0, 0.3);
+    const double X = uniform(0.2, 4.0);
+    if (X <= d.x0 + 0.05) continue;
+    d.dx = (X - d.x0) / (d.nx - 1);
+    const double T = (d.nt - 1) * d.dt;
+    d.ntau = uniform_int(4, 600);
+    d.tau0 = uniform_int(0, 2) ? 0.0 : uniform(0.0, 0.2 * T);
+    d.dtau = (T - d.tau0) / (d.ntau - 1) * uniform(0.5, 1.0);
+    d.nq = uniform_int(4, 200);
+    d.q0 = uniform(0.0, 0.4);
+    d.dq = (uniform(d.q0 + 0.05, 1.0) - d.q0) / (d.nq - 1);
+    d.oversample = ovs[uniform_int(0, 4)];
+    d.flags = variants[uniform_int(0, 5)];
+    Geometry g;
+    std::string err;
+    if (build_geometry(d, 163840 - 4096, g, err, nullptr) != HRT_OK) continue;
+    run(("random " + std::to_string(done)).c_str(), d, nullptr);
+    ++done;
+  }
+}
+
 int main() {
   const double qmin = 0.25, qmax = 1.0 / 1.5;
   hrt_desc c1{256, 128, 0.004, 0.0, 2.0 / 127, 256, 128, 0.0, 0.004, qmin,
@@ -250,6 +301,7 @@ int main() {
     }
     run(("ragged part " + std::to_string(p)).c_str(), sub, &v);
   }
+  run_random(24);
   if (fails) return 1;
   std::printf("ok\n");
   return 0;
