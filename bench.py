@@ -20,6 +20,7 @@ import argparse
 import csv
 import glob
 import hashlib
+import re
 import json
 import os
 import sys
@@ -63,14 +64,26 @@ def kernel_alg_bytes(info, desc):
             radon, radon, spec, 2 * spec + kmul, spec, data_out]
 
 
+_CODE_TOKENS = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'', re.S)
+
+
+def strip_comments(text):
+    """C++ source without its comments, trailing blanks and blank lines
+    (string and character literals kept as they are)."""
+    code = _CODE_TOKENS.sub(lambda m: "" if m.group(0).startswith("/") else m.group(0), text)
+    return "\n".join(ln.rstrip() for ln in code.splitlines() if ln.strip())
+
+
 def kernel_source_hash():
-    """Hash of the HIP sources, to tell whether stored counters still apply."""
+    """Hash of the HIP sources' code (comments and blank lines left out), to
+    tell whether stored counters still apply."""
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_1604_07651_amd", "csrc")
     for fn in sorted(os.listdir(src)):
         if fn.endswith((".hpp", ".hip", ".cpp")):
-            with open(os.path.join(src, fn), "rb") as fh:
-                h.update(fn.encode() + b"\0" + fh.read())
+            with open(os.path.join(src, fn), encoding="utf-8") as fh:
+                code = strip_comments(fh.read())
+            h.update(fn.encode() + b"\0" + code.encode())
     return h.hexdigest()[:16]
 
 

@@ -10,8 +10,9 @@
 // entries of 16 bytes (data) or 8 bytes (Radon, the angle coordinate and
 // weight coming from a per-slowness table); everything on the lattice is
 // float32 with float32 accumulation, except inside one chunk of the
-// spread, whose float32 taps are summed exactly in 64-bit fixed point and
-// rounded once to float32.
+// spread, whose taps (float64 products of a float32 sample and its float32
+// B-spline weights) are summed exactly in 64-bit fixed point and rounded
+// once to float32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -82,3 +82,21 @@ def test_profile_summaries_from_csv(tmp_path, monkeypatch):
     t["source_hash"] = "0" * 16
     json.dump(t, open(bench.TRAFFIC_FILE, "w"))
     assert bench.stored_traffic("k_spread<1, false>") is None
+
+
+def test_kernel_hash_ignores_comments_only(tmp_path, monkeypatch):
+    """The stored counters follow the kernels' code: a comment or blank-line
+    edit keeps kernel_source_hash, a change of code (string literals
+    included) changes it."""
+    src = tmp_path / "paper_1604_07651_amd" / "csrc"
+    src.mkdir(parents=True)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (src / "k.hip").write_text('int a = 1;  // one\nconst char* s = "x // y";\n')
+    h0 = bench.kernel_source_hash()
+    (src / "k.hip").write_text('/* block\n comment */\nint a = 1;\n\n'
+                               'const char* s = "x // y";  // trailing\n')
+    assert bench.kernel_source_hash() == h0
+    (src / "k.hip").write_text('int a = 2;\nconst char* s = "x // y";\n')
+    assert bench.kernel_source_hash() != h0
+    (src / "k.hip").write_text('int a = 1;\nconst char* s = "x // z";\n')
+    assert bench.kernel_source_hash() != h0
