@@ -3,7 +3,9 @@ drawn at random (every axis ragged against the kernels' tiles), forward and
 adjoint through the C ABI against the FP64 oracle, at the tolerances of the
 fixed-grid parity tests (rel-L2 <= 1e-5, max abs error <= 1e-4 of the
 reference's peak).  A grid the plan rejects is drawn again; lattices above
-4 M cells are skipped so that the oracle finishes each case in seconds."""
+4 M cells are skipped so that the oracle finishes each case in seconds.
+Uneven batches of such grids (every member, both directions, with kernel
+variants that all members take) meet the same bars."""
 import numpy as np
 import pytest
 
@@ -20,7 +22,7 @@ N_GRIDS = 32
 MAX_CELLS = 4_000_000
 
 
-def draw_grids(seed=2026, n=N_GRIDS):
+def draw_grids(seed=2026, n=N_GRIDS, max_cells=MAX_CELLS):
     """Seeded random grids that the plan accepts (host-only check)."""
     from paper_1604_07651_amd import hrt
     rng = np.random.default_rng(seed)
@@ -48,7 +50,7 @@ def draw_grids(seed=2026, n=N_GRIDS):
             info = hrt.describe(d)
         except Exception:
             continue
-        if info["m_theta"] * info["m_rho"] > MAX_CELLS:
+        if info["m_theta"] * info["m_rho"] > max_cells:
             continue
         out.append(d)
     return out
@@ -97,3 +99,22 @@ def test_random_grid_parity(i):
     compare(got, ora.adjoint(g), f"adjoint grid {i}")
     assert np.all(got[~ora.geo.keep] == 0.0)
     plan.close()
+
+
+@pytest.mark.parametrize("flags", [0, 8 | 32, 16 | 64])
+def test_random_batch_parity(flags):
+    from paper_1604_07651_amd.hrt import Batch
+    descs = draw_grids(seed=7 + flags, n=6, max_cells=1_500_000)
+    b = Batch(descs, flags=flags)
+    pairs = [synth.random_pair(d, 200 + i) for i, d in enumerate(descs)]
+    print(f"[gpu] random batch of {len(descs)}, flags {flags}", flush=True)
+    gb = b.forward(b.pack_data([p[0] for p in pairs]))
+    fb = b.adjoint(b.pack_radon([p[1] for p in pairs]))
+    torch.cuda.synchronize()
+    for i, d in enumerate(descs):
+        ora = logpolar.LogPolarOracle(d)
+        compare(b.unpack_radon(gb)[i].cpu().numpy(), ora.forward(pairs[i][0]),
+                f"batch member {i} forward")
+        compare(b.unpack_data(fb)[i].cpu().numpy(), ora.adjoint(pairs[i][1]),
+                f"batch member {i} adjoint")
+    b.close()
