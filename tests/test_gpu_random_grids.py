@@ -5,12 +5,14 @@ fixed-grid parity tests (rel-L2 <= 1e-5, max abs error <= 1e-4 of the
 reference's peak).  A grid the plan rejects is drawn again; lattices above
 4 M cells are skipped so that the oracle finishes each case in seconds.
 Uneven batches of such grids (every member, both directions, with kernel
-variants that all members take) meet the same bars."""
+variants that all members take), and such grids cut at random into time and
+slowness bands (against the oracle's split), meet the same bars."""
 import numpy as np
 import pytest
 
 import synth
 from oracle import logpolar
+from oracle import split as osplit
 
 torch = pytest.importorskip("torch")
 
@@ -118,3 +120,53 @@ def test_random_batch_parity(flags):
         compare(b.unpack_data(fb)[i].cpu().numpy(), ora.adjoint(pairs[i][1]),
                 f"batch member {i} adjoint")
     b.close()
+
+
+def draw_splits(seed=11, n=6):
+    """Seeded random grids with random cuts in time and slowness (one to three
+    bands per axis), every part accepted by the plan (host-only check)."""
+    from paper_1604_07651_amd import hrt
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        d = draw_grids(seed=int(rng.integers(1 << 30)), n=1, max_cells=1_000_000)[0]
+
+        def edges(m, bands):
+            cuts = sorted(rng.choice(np.arange(8, m - 7), size=bands - 1, replace=False).tolist()) \
+                if m > 16 + 8 * bands else []
+            return [0] + [int(c) for c in cuts] + [m]
+        te = edges(d.nt, int(rng.integers(1, 4)))
+        qe = edges(d.nq, int(rng.integers(1, 4)))
+        if np.min(np.diff(te)) < 8 or np.min(np.diff(qe)) < 8:
+            continue
+        try:
+            for part in range((len(te) - 1) * (len(qe) - 1)):
+                hrt.describe_part(d, te, qe, part)
+        except Exception:
+            continue
+        out.append((d, te, qe))
+    return out
+
+
+@pytest.mark.parametrize("i", range(6))
+def test_random_split_parity(i):
+    from paper_1604_07651_amd.hrt import Split
+    desc, te, qe = draw_splits()[i]
+    print(f"[split] random {i}: {desc} t {te} q {qe}", flush=True)
+    sp = Split(desc, te, qe)
+    ora = osplit.SplitOracle(desc, te, qe)
+    f, g = synth.random_pair(desc, 300 + i)
+    print(f"[gpu] split forward random {i}", flush=True)
+    out = torch.full(sp.radon_shape, float("nan"), device="cuda")
+    sp.forward(to_gpu(f), out=out)
+    torch.cuda.synchronize()
+    compare(out.cpu().numpy(), ora.forward(f), f"split forward {i}")
+    print(f"[gpu] split adjoint random {i}", flush=True)
+    outa = torch.full(sp.data_shape, float("nan"), device="cuda")
+    sp.adjoint(to_gpu(g), out=outa)
+    torch.cuda.synchronize()
+    ref = ora.adjoint(g)
+    got = outa.cpu().numpy()
+    compare(got, ref, f"split adjoint {i}")
+    assert np.all(got[ref == 0.0] == 0.0)
+    sp.close()
