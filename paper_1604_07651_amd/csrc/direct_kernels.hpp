@@ -22,8 +22,14 @@ __device__ __forceinline__ float keys_far(float s) {   // 1 < |s| < 2
 }
 
 // Hyperbola time in samples and the Keys weights of taps j0-1 .. j0+2; both
-// directions call this so the adjoint is the exact transpose.
+// directions call these so the adjoint is the exact transpose.  The time is
+// computed without fused multiply-adds (contraction off here): otherwise the
+// compiler fuses it with the caller's code in ways that depend on which
+// index is loop-invariant there (tau^2 + (qx)^2 fused on either product,
+// the division by dt fused with the caller's subtraction of the floor), and
+// the forward and adjoint kernels would place the same tap an ulp apart.
 __device__ __forceinline__ float hyper_c(const DirectGeo& D, int i, int l, int k) {
+#pragma clang fp contract(off)
   const float tau = D.tau0 + static_cast<float>(i) * D.dtau;
   const float qx = (D.q0 + static_cast<float>(l) * D.dq) *
                    (D.x0 + static_cast<float>(k) * D.dx);
@@ -97,6 +103,101 @@ __global__ __launch_bounds__(256) void k_direct_adj(DirectGeo D,
   }
   const float wk = (k == 0 || k == D.nx - 1) ? 0.5f * D.dx : D.dx;
   f[static_cast<size_t>(k) * D.nt + m] = wk * acc;
+}
+
+// Bytes of dynamic LDS k_direct_adj_rows takes: a slowness's four weighted
+// panel rows and its taus' tap bases (ntau each), the first-tau table
+// (nt + 4) and the trace's sums (nt).
+inline size_t direct_adj_rows_bytes(int nt, int ntau) {
+  return sizeof(float) * (5 * static_cast<size_t>(ntau) + 2 * static_cast<size_t>(nt) + 4);
+}
+
+// The same transpose, one workgroup per trace k (kDirectThreads threads).
+// For every slowness l in turn, each tau's hyperbola time c_i = hyper_c(i,
+// l, k), its tap base j_i = floor(c_i) and its four Keys weights (keys4, as
+// the forward computes them) are formed once; LDS holds v_d[i] = g[l][i] *
+// w_d(c_i - j_i) for d = 0 .. 3 and j_i.  Since tau >= 0, c_i never
+// decreases with i (every float operation in hyper_c is monotone), so with
+// I(j) the first i with j_i >= j (tabulated from the steps of j_i), the
+// taus whose tap d lands on sample m, j_i = m + 1 - d, are the run I(m + 1
+// - d) <= i < I(m + 2 - d).  The thread owning sample m adds v_3, v_2, v_1,
+// v_0 over those four runs, in increasing i, and that slowness's sum to the
+// sample's total: every output sample is summed by one thread in a fixed
+// order (deterministic, no atomics), and only taus whose taps reach the
+// sample are visited.  The next slowness's panel row is loaded into
+// registers while the current one is summed.
+constexpr int kDirectThreads = 1024;
+constexpr int kDirectRowRegs = 4;  // panel-row values a thread prefetches
+__global__ __launch_bounds__(kDirectThreads) void k_direct_adj_rows(DirectGeo D,
+                                                                    const float* __restrict__ g,
+                                                                    float* __restrict__ f) {
+  extern __shared__ float sm_direct[];
+  const int nt = D.nt, ntau = D.ntau, k = blockIdx.x;
+  float* v = sm_direct;                                 // [4][ntau]: v_d at d * ntau
+  int* jb = reinterpret_cast<int*>(v + 4 * ntau);       // [ntau]: tap bases
+  int* first = jb + ntau;                               // [nt + 4]: I(j) at j + 2
+  float* acc = reinterpret_cast<float*>(first + nt + 4);  // [nt]
+  for (int m = threadIdx.x; m < nt; m += kDirectThreads) acc[m] = 0.0f;
+  // a thread's share of a panel row, prefetched a slowness ahead (rows
+  // longer than kDirectRowRegs * kDirectThreads read the rest directly)
+  float pre[kDirectRowRegs];
+  auto load_row = [&](int l) {
+    const float* row = g + static_cast<size_t>(l) * ntau;
+#pragma unroll
+    for (int r = 0; r < kDirectRowRegs; ++r) {
+      const int i = threadIdx.x + r * kDirectThreads;
+      pre[r] = i < ntau ? row[i] : 0.0f;
+    }
+  };
+  auto stage = [&](int i, int l, float gv) {
+    const float c = hyper_c(D, i, l, k);
+    const float fl = floorf(c);
+    float w[4];
+    keys4(c - fl, w);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) v[d * ntau + i] = gv * w[d];
+    jb[i] = static_cast<int>(fl);
+  };
+  load_row(0);
+  for (int l = 0; l < D.nq; ++l) {
+    __syncthreads();  // the previous slowness is done with v, jb and first
+#pragma unroll
+    for (int r = 0; r < kDirectRowRegs; ++r) {
+      const int i = threadIdx.x + r * kDirectThreads;
+      if (i < ntau) stage(i, l, pre[r]);
+    }
+    for (int i = threadIdx.x + kDirectRowRegs * kDirectThreads; i < ntau; i += kDirectThreads)
+      stage(i, l, g[static_cast<size_t>(l) * ntau + i]);
+    __syncthreads();
+    const int jf = jb[0], jl = jb[ntau - 1];
+    // I(j) for jf < j <= jl, only where a sample reads it (j in [-2, nt + 1])
+    for (int i = threadIdx.x + 1; i < ntau; i += kDirectThreads) {
+      const int lo = max(jb[i - 1] + 1, -2), hi = min(jb[i], nt + 1);
+      for (int j = lo; j <= hi; ++j) first[j + 2] = i;
+    }
+    if (l + 1 < D.nq) load_row(l + 1);
+    __syncthreads();
+    for (int m = threadIdx.x; m < nt; m += kDirectThreads) {
+      // b[q] = I(m - 2 + q), q = 0 .. 4
+      int b[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const int j = m - 2 + q;
+        b[q] = j <= jf ? 0 : (j > jl ? ntau : first[j + 2]);
+      }
+      float s = 0.0f;
+#pragma unroll
+      for (int d = 3; d >= 0; --d) {  // tap d: taus with j_i = m + 1 - d
+        const float* vd = v + d * ntau;
+        for (int i = b[3 - d]; i < b[4 - d]; ++i) s += vd[i];
+      }
+      acc[m] += s;
+    }
+  }
+  __syncthreads();
+  const float wk = (k == 0 || k == D.nx - 1) ? 0.5f * D.dx : D.dx;
+  for (int m = threadIdx.x; m < nt; m += kDirectThreads)
+    f[static_cast<size_t>(k) * nt + m] = wk * acc[m];
 }
 
 }  // namespace hrt

@@ -65,6 +65,7 @@ struct hrt_plan_s {
   hrt_info info;
   DevGeo dg;
   DirectGeo dd;
+  int64_t direct_rows_bytes = 0;  // LDS of k_direct_adj_rows; 0: use k_direct_adj
   FftDev ft, fr;
   float2* S = nullptr;
   float2* K = nullptr;
@@ -612,6 +613,26 @@ static hrt_status create_plan(const hrt_desc* desc, const PartView* view, hrt_pl
         return hip_err(r, "hipFuncSetAttribute");
       }
     }
+    // the direct adjoint stages a slowness's hyperbola times and panel row
+    // in LDS when they fit; otherwise it takes the per-sample search
+    {
+      const void* fn = reinterpret_cast<const void*>(&k_direct_adj_rows);
+      hipFuncAttributes fa;
+      hipError_t r = hipFuncGetAttributes(&fa, fn);
+      if (r == hipSuccess) {
+        const int64_t room = cap - static_cast<int64_t>(fa.sharedSizeBytes);
+        r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(room));
+        const int64_t need = static_cast<int64_t>(direct_adj_rows_bytes(g.d.nt, g.d.ntau));
+        if (r == hipSuccess && need <= room) p->direct_rows_bytes = need;
+      }
+      if (r != hipSuccess) {
+        (void)hipGetLastError();
+        free_plan(p);
+        delete p;
+        return hip_err(r, "direct adjoint attributes");
+      }
+    }
   }
   DevGeo& G = p->dg;
   G.nt = g.d.nt; G.nx = g.d.nx;
@@ -1097,6 +1118,7 @@ hrt_status hrt_direct_forward(hrt_plan_t p, const float* f, float* g, void* stre
   DeviceGuard guard(p->device);
   const DirectGeo& D = p->dd;
   dim3 grid((D.ntau + 255) / 256, D.nq);
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
   k_direct_fwd<<<grid, 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(D, f, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, "direct forward launch");
@@ -1109,8 +1131,15 @@ hrt_status hrt_direct_adjoint(hrt_plan_t p, const float* g, float* f, void* stre
   if (!f || !g) return set_err(HRT_ERR_INVALID_ARG, "null array");
   DeviceGuard guard(p->device);
   const DirectGeo& D = p->dd;
-  dim3 grid((D.nt + 255) / 256, D.nx);
-  k_direct_adj<<<grid, 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(D, g, f);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
+  if (p->direct_rows_bytes > 0) {
+    k_direct_adj_rows<<<D.nx, kDirectThreads, static_cast<size_t>(p->direct_rows_bytes), st>>>(
+        D, g, f);
+  } else {
+    dim3 grid((D.nt + 255) / 256, D.nx);
+    k_direct_adj<<<grid, 256, 0, st>>>(D, g, f);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, "direct adjoint launch");
   return HRT_OK;

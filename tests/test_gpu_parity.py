@@ -307,6 +307,55 @@ def test_direct_sum_matches_oracle():
     assert abs(lhs - rhs) / abs(lhs) <= 1e-5
 
 
+# direct-sum grids: offsets in time and space, a tau step of 3.75 time
+# samples (one tau moves the taps by several samples), and a panel row too
+# long for the adjoint's LDS staging (4 (5 ntau + 2 nt + 4) bytes > 160 KiB:
+# the per-sample search kernel; many taus on a short trace, since the
+# float32 hyperbola times of long traces, good to c 2^-24 samples, hold the
+# direct forward of white noise near 1e-4 of the float64 one already at
+# 2048 samples)
+DIRECT_GRIDS = {
+    "odd": SMALL["odd"],
+    "ragged": SMALL["ragged"],
+    "coarse_tau": synth.GridDesc(nt=400, nx=40, dt=0.002, x0=0.1, dx=0.05, ntau=100, nq=30,
+                                 tau0=0.05, dtau=0.0075, q0=0.2, dq=0.015),
+    "many_taus": synth.GridDesc(nt=512, nx=6, dt=0.002, x0=0.0, dx=0.3, ntau=20000, nq=6,
+                                tau0=0.0, dtau=511 * 0.002 / 19999, q0=0.25, dq=0.08),
+}
+
+
+@pytest.mark.parametrize("name", list(DIRECT_GRIDS))
+def test_direct_sum_paths_match_oracle(name):
+    """Both directions of the GPU direct sum against the oracle's, the
+    float32 transpose identity between them, and a repeated adjoint bit for
+    bit the same (its sums run in a fixed order)."""
+    from paper_1604_07651_amd.hrt import Plan
+    desc = DIRECT_GRIDS[name]
+    staged = 4 * (5 * desc.ntau + 2 * desc.nt + 4) <= 163840
+    print(f"[plan] direct {name} (adjoint {'staged rows' if staged else 'search'})", flush=True)
+    plan = Plan(desc)
+    f, g = synth.random_pair(desc, 44)
+    F, G = to_gpu(f), to_gpu(g)
+    print(f"[gpu] direct {name}", flush=True)
+    got = plan.direct_forward(F)
+    gota = plan.direct_adjoint(G)
+    gotb = plan.direct_adjoint(G)
+    torch.cuda.synchronize()
+    assert torch.equal(gota, gotb)
+    for what, y, ref in (("forward", got, direct.forward(desc, f)),
+                         ("adjoint", gota, direct.adjoint(desc, g))):
+        y = y.double().cpu().numpy()
+        r = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+        print(f"  direct {what} rel-L2 {r:.2e}", flush=True)
+        assert r <= 1e-4
+    lhs = torch.sum(got.double() * G.double()).item()
+    rhs = torch.sum(F.double() * gota.double()).item()
+    err = abs(lhs - rhs) / (got.double().norm().item() * G.double().norm().item())
+    print(f"  direct transpose identity {err:.2e}", flush=True)
+    assert err <= 1e-5
+    plan.close()
+
+
 def test_direct_sum_matches_oracle_c2():
     """The GPU direct sum (the reference the metric compares against) at C2:
     forward on a sample of 16 slowness rows, adjoint of a panel whose only
