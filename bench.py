@@ -745,9 +745,9 @@ def main():
                      "ms_fwd_adj": round(sec_per_step * 1e3, 5)},
         "tuning": tuning,
         # the forward-only ratio is the comparator headline: the GPU direct
-        # adjoint is a gather with a tau search per sample, several times
-        # slower than the direct forward, so the forward+adjoint ratio
-        # flatters the log-polar method
+        # adjoint (staged per slowness and trace, three barriers per pair)
+        # costs about four times the direct forward, so the forward+adjoint
+        # ratio flatters the log-polar method
         "direct_sum": {"speedup_headline_fwd": round(direct_fwd_sec / lp_fwd_sec, 1),
                        "gathers_per_s": round(1.0 / direct_sec, 3),
                        "ms_fwd_adj": round(direct_sec * 1e3, 3),
