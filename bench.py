@@ -188,6 +188,64 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, commands, source_hash):
     print(f"wrote {md} and {TRAFFIC_FILE}")
 
 
+def summarize_batch_trace(trace_dir, commands, source_hash, reps):
+    """The kernel trace of `--profile-batch` (the 64-gather uneven batch,
+    forward+adjoint with one launch per kernel) as profiles/c4_batch_kernels.md:
+    per batched kernel its launches, average duration and its time per
+    forward+adjoint of the whole batch (the trace holds `reps` passes and
+    the one warm-up pass before them)."""
+    stats = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not stats:
+        raise SystemExit("missing rocprofv3 kernel statistics")
+    rows = []
+    with open(stats[0]) as fh:
+        for row in csv.DictReader(fh):
+            name = short_kernel_name(row["Name"])
+            if name.startswith("k_") and "true>" in name:
+                calls, avg = int(row["Calls"]), float(row["AverageNs"]) / 1e3
+                rows.append((name, calls, avg, calls * avg / (reps + 1)))
+    total = sum(r[3] for r in rows)
+    md = os.path.join(ROOT, "profiles", "c4_batch_kernels.md")
+    with open(md, "w") as fh:
+        fh.write("# Kernel trace, uneven batch of 64 gathers (nt in {512, 1024, 2048}, "
+                 "nx = nq in 128..1024), forward+adjoint, one launch per kernel\n\n")
+        fh.write("Commands (run from the repository root on one MI355X):\n\n")
+        for c in commands:
+            fh.write(f"    {c}\n")
+        fh.write(f"\nThe trace holds {reps + 1} forward+adjoint passes of the batch (one "
+                 "warm-up pass, then the timed ones); us per pass = launches x average / "
+                 f"{reps + 1}.\n\n"
+                 "| kernel | launches | avg us | us per batch pass | share |\n"
+                 "|---|---|---|---|---|\n")
+        for k, n, us, per in sorted(rows, key=lambda r: -r[3]):
+            fh.write(f"| {k} | {n} | {us:.2f} | {per:.1f} | {100 * per / total:.1f} % |\n")
+        fh.write(f"\nBatched kernels per forward+adjoint of the batch: {total / 1e3:.3f} ms.\n")
+        fh.write(f"\nKernel source hash: {source_hash}\n")
+    print(f"wrote {md}")
+
+
+def profile_batch(torch, np, reps):
+    """Only the 64-gather batch's forward+adjoint (one untimed pass, then
+    `reps` timed ones), for a kernel trace of the batched kernels."""
+    import synth
+    from paper_1604_07651_amd.hrt import Batch
+    descs = synth.batch_descs(64, seed=4)
+    b = Batch(descs)
+    F = b.pack_data(synth.batch_gathers(descs))
+    g = b.forward(F)
+    fa = b.adjoint(g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.forward(F, out=g)
+        b.adjoint(g, out=fa)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    print(json.dumps({"batch_c4_passes": reps, "ms_per_batch": round(sec * 1e3, 3),
+                      "kernel_source_hash": kernel_source_hash()}))
+    b.close()
+
+
 def stored_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counters, or None
     if they were taken on other kernel sources."""
@@ -556,6 +614,11 @@ def main():
                     help="write profiles/c3_sq_counters.md from rocprofv3 --pmc CSV "
                          "directories (no GPU needed)")
     ap.add_argument("--profile-commands", nargs="*", default=[])
+    ap.add_argument("--profile-batch", type=int, default=0, metavar="PASSES",
+                    help="run only PASSES forward+adjoint passes of the 64-gather batch "
+                         "(after one untimed pass), for a kernel trace")
+    ap.add_argument("--summarize-batch-trace", metavar="TRACE",
+                    help="write profiles/c4_batch_kernels.md from a --profile-batch trace")
     ap.add_argument("--profile-hash", default="",
                     help="kernel_source_hash printed by the profiled runs")
     args = ap.parse_args()
@@ -564,6 +627,10 @@ def main():
         return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, args.profile_commands, args.profile_hash)
+        return
+    if args.summarize_batch_trace:
+        summarize_batch_trace(args.summarize_batch_trace, args.profile_commands,
+                              args.profile_hash, args.profile_batch or 10)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the transform of a gather runs on "
@@ -578,6 +645,9 @@ def main():
     from paper_1604_07651_amd.hrt import Plan
 
     torch.cuda.set_device(0)
+    if args.profile_batch:
+        profile_batch(torch, np, args.profile_batch)
+        return
     desc = synth.config_desc("c3")
     log("generating the gather")
     f64 = synth.config_gather("c3")

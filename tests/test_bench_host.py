@@ -100,3 +100,23 @@ def test_kernel_hash_ignores_comments_only(tmp_path, monkeypatch):
     assert bench.kernel_source_hash() != h0
     (src / "k.hip").write_text('int a = 1;\nconst char* s = "x // z";\n')
     assert bench.kernel_source_hash() != h0
+
+
+def test_batch_trace_summary(tmp_path, monkeypatch):
+    """The batch trace summary keeps the batched kernels only and gives each
+    its time per forward+adjoint pass (launches x average over the passes
+    the trace holds: the timed ones and the warm-up)."""
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    _write_csv(str(tmp_path / "trace" / "run_kernel_stats.csv"),
+               ["Name", "Calls", "AverageNs", "Percentage"],
+               [["void hrt::k_spread<1, true>(hrt::DevGeo, int2 const*, float const*)", 11,
+                 500000.0, 40.0],
+                ["void hrt::k_spread<1, false>(hrt::DevGeo, int2 const*, float const*)", 3,
+                 30000.0, 1.0],
+                ["__amd_rocclr_copyBuffer", 4, 3000.0, 0.1]])
+    bench.summarize_batch_trace(str(tmp_path / "trace"), ["cmd"], "abc", 10)
+    text = (tmp_path / "profiles" / "c4_batch_kernels.md").read_text()
+    assert "| k_spread<1, true> | 11 | 500.00 | 500.0 | 100.0 % |" in text
+    assert "k_spread<1, false>" not in text and "copyBuffer" not in text
+    assert "0.500 ms" in text and "Kernel source hash: abc" in text
