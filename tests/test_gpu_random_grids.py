@@ -6,11 +6,15 @@ reference's peak).  A grid the plan rejects is drawn again; lattices above
 4 M cells are skipped so that the oracle finishes each case in seconds.
 Uneven batches of such grids (every member, both directions, with kernel
 variants that all members take), and such grids cut at random into time and
-slowness bands (against the oracle's split), meet the same bars."""
+slowness bands (against the oracle's split), meet the same bars; so do the
+soft-thresholding iterations (half the traces masked) and the multiple
+attenuation on random grids, against the oracle's."""
 import numpy as np
 import pytest
 
 import synth
+from oracle import demultiple as odemultiple
+from oracle import ista as oista
 from oracle import logpolar
 from oracle import split as osplit
 
@@ -24,7 +28,7 @@ N_GRIDS = 32
 MAX_CELLS = 4_000_000
 
 
-def draw_grids(seed=2026, n=N_GRIDS, max_cells=MAX_CELLS):
+def draw_grids(seed=2026, n=N_GRIDS, max_cells=MAX_CELLS, max_samples=None):
     """Seeded random grids that the plan accepts (host-only check)."""
     from paper_1604_07651_amd import hrt
     rng = np.random.default_rng(seed)
@@ -53,6 +57,8 @@ def draw_grids(seed=2026, n=N_GRIDS, max_cells=MAX_CELLS):
         except Exception:
             continue
         if info["m_theta"] * info["m_rho"] > max_cells:
+            continue
+        if max_samples and nt * nx + ntau * nq > max_samples:
             continue
         out.append(d)
     return out
@@ -170,3 +176,50 @@ def test_random_split_parity(i):
     compare(got, ref, f"split adjoint {i}")
     assert np.all(got[ref == 0.0] == 0.0)
     sp.close()
+
+
+@pytest.mark.parametrize("i", range(3))
+def test_random_grid_ista_and_demultiple(i):
+    """Twelve soft-thresholding iterations with half the traces masked (eq.
+    itersmd), and the multiple attenuation (mute above a sloping border,
+    adjoint, subtract), on random grids against the float64 oracle."""
+    from paper_1604_07651_amd.hrt import Plan
+    desc = draw_grids(seed=31 + i, n=1, max_cells=200_000, max_samples=150_000)[0]
+    print(f"[plan] random ista/demultiple {i}: {desc}", flush=True)
+    plan = Plan(desc)
+    ora = logpolar.LogPolarOracle(desc)
+    f, g = synth.random_pair(desc, 400 + i)
+    keep = synth.trace_mask(desc.nx, 0.5, 500 + i)
+    mask = np.repeat(keep[:, None], desc.nt, axis=1).astype(np.float64)
+    f = f * mask
+    lam = oista.power_norm2(ora.forward, ora.adjoint, plan.data_shape, iters=40, seed=3)
+    c2 = 0.99 / lam
+    mu = 0.05 * np.abs(ora.forward(f)).max()
+    ref = oista.ista(ora.forward, ora.adjoint, f, 12, c2, mu, mask)
+    gg = torch.zeros(plan.radon_shape, device="cuda")
+    print(f"[gpu] ista random {i}", flush=True)
+    plan.ista_iterate(to_gpu(f), gg, 12, c2, mu, mask=to_gpu(mask))
+    torch.cuda.synchronize()
+    got = gg.cpu().numpy().astype(np.float64)
+    r = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"  ista rel-L2 {r:.2e}", flush=True)
+    assert r <= 2e-5
+    qb0 = desc.q0 + 0.5 * (desc.nq - 1) * desc.dq
+    slope = 0.05
+    print(f"[gpu] demultiple random {i}", flush=True)
+    out = plan.demultiple(to_gpu(f), to_gpu(g), qb0, slope)
+    torch.cuda.synchronize()
+    refd = odemultiple.demultiple(ora.adjoint, desc, f, g, qb0, slope)
+    r = np.linalg.norm(out.cpu().numpy().astype(np.float64) - refd) / np.linalg.norm(refd)
+    print(f"  demultiple rel-L2 {r:.2e}", flush=True)
+    assert r <= 1e-5
+    # the part removed on its own (a zero gather: the output is minus the
+    # adjoint of the muted panel, with no float32 subtraction hiding it)
+    zero = np.zeros_like(f)
+    out0 = plan.demultiple(to_gpu(zero), to_gpu(g), qb0, slope)
+    torch.cuda.synchronize()
+    ref0 = odemultiple.demultiple(ora.adjoint, desc, zero, g, qb0, slope)
+    r = np.linalg.norm(out0.cpu().numpy().astype(np.float64) - ref0) / np.linalg.norm(ref0)
+    print(f"  demultiple removed part rel-L2 {r:.2e}", flush=True)
+    assert r <= 1e-5
+    plan.close()
