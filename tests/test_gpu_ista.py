@@ -160,6 +160,14 @@ def test_demultiple_matches_oracle():
         r = rel(out.cpu().numpy(), ref)
         print(f"  demultiple rel-L2 {r:.2e}", flush=True)
         assert r <= 1e-5
+        # the removed part alone (zero gather: the output is minus the
+        # adjoint of the muted panel)
+        zero = np.zeros_like(f)
+        out0 = plan.demultiple(to_gpu(zero), to_gpu(g), qb0, slope)
+        torch.cuda.synchronize()
+        r = rel(out0.cpu().numpy(), demultiple.demultiple(ora.adjoint, desc, zero, g, qb0, slope))
+        print(f"  removed part rel-L2 {r:.2e}", flush=True)
+        assert r <= 1e-5
 
 
 def test_demultiple_pipeline_attenuates_multiples_on_gpu():
